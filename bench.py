@@ -1,0 +1,141 @@
+"""Benchmark of the jet-LES hot path on one MI355X.
+
+Default workload: one GPU's share of a production jet mesh -- the 512 x 256 x
+256 separable tanh-stretched periodic grid (33.5M nodes) with analytic FP64
+metrics, Mach 1.4 round jet at Re_D = 1e6 with 1 % seeded velocity noise,
+advanced by the FP64 fused residual + five-stage RK path.  One "step" is one
+full RK step (five fused stage kernels, the norm and dt reductions).
+
+Prints one JSON line: point-stage updates per second (N x 5 x steps / time)
+with the inputs resident in HBM, the roofline record of the stage kernel
+(algorithmic bytes per launch / mean launch time from HIP events), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (512, 256, 256)
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def _kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("jz_stage.hip", "jz_internal.h"):
+        with open(os.path.join(ROOT, "paper_2003_09926_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec or rec.get("kernel_hash") != _kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(min_seconds: float = 10.0):
+    """The oracle, as it stands, on the stride-4 subsample of the workload
+    (128 x 64 x 64 nodes, same grid family and jet), stepped until at least
+    ``min_seconds`` have elapsed."""
+    import oracle
+    from paper_2003_09926_amd import inputs as I
+    g, q = I.stretched_jet_case(DIMS, seed=2, stride=4)
+    P = oracle.default_params(re_d=1.0e6)
+    oracle.step(g.dims, P, g.metrics, q)          # warm (page-in, thread pool)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        q, _, _, _ = oracle.step(g.dims, P, g.metrics, q)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds and steps >= 2:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": g.n * 5 * steps / el, "unit": "point-stage updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the 128x64x64 stride-4 subsample of the 512x256x256 "
+                      f"stretched jet grid (FP64 C++ oracle, OpenMP), {el:.1f} s"}
+
+
+def run_fp64(steps: int, warmup: int, with_cpu: bool):
+    import torch
+    from paper_2003_09926_amd import binding as B
+    from paper_2003_09926_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    g, q = I.stretched_jet_case(DIMS, seed=2)
+    P = B.params_default(re_d=1.0e6)
+    s = B.Solver(g.dims, P)
+    s.set_grid_metrics(g.metrics)
+    s.set_state(q)
+    del q
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stage_ms, launches, stage_bytes = s.timing()
+    s.set_timing(False)
+    s.residual_norms()     # raises if the run went non-finite
+    s.close()
+    n = g.n
+    value = n * 5 * steps / el
+    avg_ms = stage_ms / max(launches, 1)
+    bytes_per_launch = stage_bytes / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic("stage_fp64")
+    out = {
+        "metric": "point-stage updates/s", "value": value, "unit": "point-stage updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": el * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "jet_512x256x256_stretched_fp64", "dims": list(DIMS), "mach": 1.4,
+                   "re_d": 1.0e6, "seed": 2, "stages_per_step": 5, "form": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "stage_fp64", "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs one GPU per process and measures one GPU; "
+                                   "--gpus above 1 is not supported"}), flush=True)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    out = run_fp64(a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu))
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,166 @@
+/* jetles.h -- C ABI of the MI355X jet-LES hot path.
+ *
+ * One solver object owns one structured, periodic, curvilinear block of
+ * ni x nj x nk nodes (xi = i streamwise, eta = j, zeta = k) resident in the
+ * HBM of one GPU, and advances the filtered compressible Navier-Stokes
+ * equations (Sec. 3 of arXiv:2003.09926, Eq. (les) with the closure of
+ * Eqs. (q_mod), (sutherland), (tau_mod)) by the explicit five-stage
+ * Runge-Kutta scheme (Sec. 3, closing paragraph; per-stage order of work in
+ * Sec. 4.2 and its flow chart).  The spatial operator is the centred
+ * second-order finite difference on curvilinear coordinates with anisotropic
+ * scalar artificial dissipation (Sec. 3) on a five-point stencil (two ghost
+ * layers, Sec. 4.3), plus a Smagorinsky subgrid viscosity.
+ *
+ * Conventions used by every entry point:
+ *   - node (i, j, k) sits at linear index n = i + ni * (j + nj * k);
+ *     N = ni * nj * nk;
+ *   - a state is 5 x N doubles, structure of arrays, variable-major:
+ *     q[v * N + n], v = rho, rho u, rho v, rho w, e (total energy per volume);
+ *   - a metric set is 10 x N doubles: m[(3 d + a) * N + n] = S^d_a, the
+ *     derivative of xi_d with respect to x_a divided by J, for d, a in
+ *     {0, 1, 2}; m[9 * N + n] = J = 1 / det d(x, y, z) / d(xi, eta, zeta);
+ *   - the block is periodic in all three directions (the periodic wrap
+ *     stands in for the neighbour ranks' ghost layers of Sec. 4.3);
+ *   - units: ambient rho = 1, p = 1/gamma, sound speed 1, jet diameter 1,
+ *     mu_inf = mach_j / re_d, Sutherland reference temperature 1;
+ *   - every function returns an int status (JZ_OK = 0, negative = error) and
+ *     never throws; jz_last_error() gives a thread-local message;
+ *   - host arrays are owned by the caller and only read (or written) during
+ *     the call; "on_device" arguments select a device pointer instead;
+ *   - all GPU work is issued on the solver's stream in call order; only the
+ *     jz_get_* calls and the calls that validate input synchronise it.
+ */
+#ifndef JETLES_H
+#define JETLES_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  JZ_OK = 0,
+  JZ_EINVAL = -1,     /* null pointer, size < 1, bad parameter, workspace too small, bad grid */
+  JZ_ENOMEM = -2,     /* device allocation failed */
+  JZ_EHIP = -3,       /* HIP runtime error; message in jz_last_error() */
+  JZ_ENONFINITE = -4, /* NaN/Inf in the state or residual norms, or dt <= 0 */
+  JZ_ESTATE = -5      /* call out of order (advance before grid and state are set) */
+};
+
+typedef struct jz_solver jz_solver; /* opaque, library-owned */
+
+typedef enum { JZ_FP64 = 0, JZ_FP32_FLUX = 1 } jz_precision;
+
+/* Physical and numerical parameters.  Values the paper leaves open carry the
+ * defaults of jz_params_default(); the paper fixes Pr = 0.72 (Sec. 3) and the
+ * number of stages (5, Sec. 3). */
+typedef struct {
+  double gamma;        /* ratio of specific heats (1.4) */
+  double prandtl;      /* molecular Prandtl number (0.72) */
+  double prandtl_t;    /* subgrid Prandtl number (0.9) */
+  double mach_j;       /* jet Mach number; also the velocity scale of mu_inf */
+  double re_d;         /* jet Reynolds number; +inf or <= 0 gives mu_inf = 0 */
+  double sutherland_s; /* Sutherland constant / reference temperature (110.4/288.15) */
+  double cs;           /* Smagorinsky constant (0.17); 0 switches the SGS model off */
+  double k2, k4;       /* dissipation coefficients (1/4, 1/64) */
+  double tv_alpha;     /* anisotropic scaling exponent (0.5) */
+  double cfl;          /* Courant number of the global time step (0.5) */
+  double dt_fixed;     /* > 0: fixed time step instead of the CFL rule (0) */
+  double rk_alpha[5];  /* stage coefficients (1/4, 1/6, 3/8, 1/2, 1) */
+  int n_stages;        /* 1..5 (5) */
+  int precision;       /* jz_precision (JZ_FP64) */
+  int tile_i, tile_j;  /* launch shape of the stage kernel; 0 = library default */
+  int kchunk;          /* planes marched per workgroup; 0 = library default */
+} jz_params;
+
+/* Fill *p with the defaults listed above. */
+int jz_params_default(jz_params* p);
+
+/* Bytes of device memory a solver of this size and precision needs when the
+ * caller provides the workspace (see jz_create).  0 on invalid sizes. */
+size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p);
+
+/* Create a solver for an ni x nj x nk block (each >= 1).
+ * dev_workspace: NULL = the library allocates (hipMalloc) and frees in
+ *   jz_destroy; otherwise a device buffer of at least ws_bytes >=
+ *   jz_workspace_bytes(...) bytes, 256-byte aligned, owned by the caller
+ *   (for example a torch tensor) and kept alive until jz_destroy.
+ * hip_stream: the hipStream_t all work is issued on (NULL = null stream).
+ * The parameters are copied.  JZ_EINVAL on bad sizes/parameters. */
+int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, size_t ws_bytes,
+              void* hip_stream, jz_solver** out);
+
+/* Geometry from node coordinates (host arrays x, y, z of N doubles each) and
+ * the periodic shift vectors period[3 d + a] (the change of coordinate a when
+ * index d wraps once forwards).  Computes the Thomas-Lombard metric set and J
+ * on the GPU in FP64 (Sec. 3: curvilinear form; Sec. 4.2: metrics computed
+ * once after the mesh is read).  JZ_EINVAL if any J is non-positive or not
+ * finite.  Synchronises. */
+int jz_set_grid_coords(jz_solver* s, const double* x, const double* y, const double* z,
+                       const double* period);
+
+/* Geometry from a metric set computed elsewhere (10 x N, layout above), e.g.
+ * the analytic metrics of a separable grid.  on_device selects a device
+ * pointer.  JZ_EINVAL if any J is non-positive or not finite.  Synchronises. */
+int jz_set_grid_metrics(jz_solver* s, const double* m, int on_device);
+
+/* Copy the metric set (10 x N) out.  Synchronises. */
+int jz_get_grid_metrics(jz_solver* s, double* m, int on_device);
+
+/* Set the conserved state (5 x N).  JZ_ENONFINITE if it holds NaN/Inf,
+ * JZ_EINVAL if rho or p is not positive somewhere; the previous state is then
+ * kept.  The next step recomputes dt from this state.  Synchronises. */
+int jz_set_state(jz_solver* s, const double* q, int on_device);
+
+/* Advance nsteps explicit five-stage steps.  Each step takes
+ * dt = cfl / max_nodes sum_d lambda^d from the state at its start (or
+ * dt_fixed), runs the stages Q(k) = Q(0) - alpha_k dt R(Q(k-1)), records the
+ * norms of the first-stage residual and advances the clock.  Asynchronous:
+ * returns once the work is queued.  If a step produces NaN/Inf norms or a
+ * non-positive dt, later kernels leave the state at that step and the next
+ * jz_get_* call returns JZ_ENONFINITE. */
+int jz_advance(jz_solver* s, int nsteps);
+
+/* Copy the state (5 x N) out.  Synchronises; JZ_ENONFINITE after a failed step
+ * (the state of the failing step is still copied). */
+int jz_get_state(jz_solver* s, double* q, int on_device);
+
+/* RMS and max-norm per conserved variable of R(Q^n) (the first stage of the
+ * last step).  Synchronises. */
+int jz_get_residual_norms(jz_solver* s, double rms[5], double linf[5]);
+
+/* Simulated time, the step size the next step will use, and the step count.
+ * Synchronises. */
+int jz_get_clock(jz_solver* s, double* t, double* next_dt, long long* steps);
+
+/* Set the simulated time and step count (checkpoint/resume). */
+int jz_set_clock(jz_solver* s, double t, long long steps);
+
+/* One evaluation of the residual R(Q) of the current state into r (5 x N),
+ * with the same kernels the stages use.  Synchronises. */
+int jz_eval_residual(jz_solver* s, double* r, int on_device);
+
+/* Time step the CFL rule gives for the current state and the maximum of
+ * sum_d lambda^d it came from.  Synchronises. */
+int jz_eval_dt(jz_solver* s, double* dt, double* lambda_max);
+
+/* Kernel timing with hipEvents on the solver's stream: enable = 1 starts
+ * recording each stage-kernel launch of jz_advance, 0 stops.  jz_get_timing
+ * synchronises and returns the summed milliseconds and launch count of the
+ * stage kernels since timing was enabled, and the algorithmic HBM bytes of
+ * those launches (each array read or written once per stage). */
+int jz_set_timing(jz_solver* s, int enable);
+int jz_get_timing(jz_solver* s, double* stage_ms, long long* stage_launches, double* stage_bytes);
+
+/* Release the solver (and the workspace if the library allocated it). */
+int jz_destroy(jz_solver* s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* jz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JETLES_H */

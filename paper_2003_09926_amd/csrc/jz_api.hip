@@ -1,0 +1,588 @@
+// jz_api.hip -- C ABI of the jet-LES library (host side).  See include/jetles.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/jetles.h"
+#include "jz_internal.h"
+
+namespace jz {
+hipError_t launch_stage_fp64(const StageArgs& a, const int* flag, int mode, int bx, int by, int nblocks,
+                             hipStream_t st);
+bool stage_shape_supported(int bx, int by);
+hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, double* m,
+                             hipStream_t st);
+hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st);
+hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st);
+int lambda_max_blocks(long long N);
+hipError_t launch_lambda_max(const double* q, const double* m, long long N, double gamma, double* part,
+                             hipStream_t st);
+hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCtl ctl, int* flag, hipStream_t st);
+hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
+                                int* flag, hipStream_t st);
+}  // namespace jz
+
+using namespace jz;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(JZ_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t q0, qa, qb, met, norm_part, lam_part, clock, flag, total;
+};
+
+void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
+  t->bx = 32;
+  t->by = 16;
+  if (p && p->tile_i > 0 && p->tile_j > 0) {
+    t->bx = p->tile_i + 4;
+    t->by = p->tile_j + 4;
+  }
+  t->ti = t->bx - 4;
+  t->tj = t->by - 4;
+  t->tiles_i = (ni + t->ti - 1) / t->ti;
+  t->tiles_j = (nj + t->tj - 1) / t->tj;
+  int kc = (p && p->kchunk > 0) ? p->kchunk : 32;
+  if (kc > nk) kc = nk;
+  t->kchunk = kc;
+  t->nchunks = (nk + kc - 1) / kc;
+  t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
+}
+
+Layout layout_for(long long N, const Tiling& t) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.q0 = take(5 * N * sizeof(double));
+  L.qa = take(5 * N * sizeof(double));
+  L.qb = take(5 * N * sizeof(double));
+  L.met = take(10 * N * sizeof(double));
+  L.norm_part = take((size_t)t.nblocks * 10 * sizeof(double));
+  const int lb = t.nblocks > lambda_max_blocks(N) ? t.nblocks : lambda_max_blocks(N);
+  L.lam_part = take((size_t)lb * sizeof(double));
+  L.clock = take(sizeof(Clock));
+  L.flag = take(4 * sizeof(int));
+  L.total = off;
+  return L;
+}
+
+bool params_ok(const jz_params* p, std::string* why) {
+  if (!p) {
+    *why = "params is NULL";
+    return false;
+  }
+  if (!(p->gamma > 1.0) || !(p->prandtl > 0) || !(p->prandtl_t > 0) || !(p->sutherland_s > 0) || !(p->cs >= 0) ||
+      !(p->k2 >= 0) || !(p->k4 >= 0) || !(p->tv_alpha >= 0) || !(p->cfl > 0) || !(p->dt_fixed >= 0) ||
+      !(p->mach_j >= 0)) {
+    *why = "a physical or numerical parameter is out of range";
+    return false;
+  }
+  if (p->n_stages < 1 || p->n_stages > 5) {
+    *why = "n_stages must be 1..5";
+    return false;
+  }
+  if (p->precision != JZ_FP64) {
+    *why = "precision must be JZ_FP64 for a single block";
+    return false;
+  }
+  if ((p->tile_i > 0) != (p->tile_j > 0)) {
+    *why = "tile_i and tile_j must both be set or both be 0";
+    return false;
+  }
+  if (p->tile_i > 0 && !stage_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
+    *why = "unsupported tile shape (supported: 28x12, 60x4, 12x28, 28x4, 12x12)";
+    return false;
+  }
+  if (p->kchunk < 0) {
+    *why = "kchunk must be >= 0";
+    return false;
+  }
+  return true;
+}
+
+Phys make_phys(const jz_params& p) {
+  Phys ph;
+  ph.gamma = p.gamma;
+  ph.gm1 = p.gamma - 1.0;
+  const double mu_inf = (p.re_d > 0.0 && std::isfinite(p.re_d)) ? p.mach_j / p.re_d : 0.0;
+  ph.mu_suth = mu_inf * (1.0 + p.sutherland_s);
+  ph.suth_s = p.sutherland_s;
+  ph.cs2 = p.cs * p.cs;
+  const double cp = 1.0 / (p.gamma - 1.0);
+  ph.kap_lam = cp / p.prandtl;
+  ph.kap_turb = cp / p.prandtl_t;
+  ph.k2 = p.k2;
+  ph.k4 = p.k4;
+  ph.tv_alpha = p.tv_alpha;
+  ph.alpha_half = (p.tv_alpha == 0.5) ? 1 : 0;
+  ph.pad = 0;
+  return ph;
+}
+
+}  // namespace
+
+struct jz_solver {
+  int ni, nj, nk;
+  long long N;
+  jz_params p;
+  Phys ph;
+  Tiling tl;
+  Layout L;
+  hipStream_t stream;
+  char* ws;
+  bool owns_ws;
+  int device;
+  bool grid_set, state_set, dt_valid;
+  double* q0;
+  double* qa;
+  double* qb;
+  double* met;
+  double* norm_part;
+  double* lam_part;
+  Clock* clock;
+  int* flag;
+  // timing
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<double> ev_bytes;
+  double stage_ms_acc;
+  long long stage_launches_acc;
+  double stage_bytes_acc;
+};
+
+extern "C" {
+
+int jz_params_default(jz_params* p) {
+  if (!p) return fail(JZ_EINVAL, "jz_params_default: NULL");
+  std::memset(p, 0, sizeof *p);
+  p->gamma = 1.4;
+  p->prandtl = 0.72;
+  p->prandtl_t = 0.9;
+  p->mach_j = 1.4;
+  p->re_d = 1.0e5;
+  p->sutherland_s = 110.4 / 288.15;
+  p->cs = 0.17;
+  p->k2 = 0.25;
+  p->k4 = 1.0 / 64.0;
+  p->tv_alpha = 0.5;
+  p->cfl = 0.5;
+  p->dt_fixed = 0.0;
+  p->rk_alpha[0] = 1.0 / 4.0;
+  p->rk_alpha[1] = 1.0 / 6.0;
+  p->rk_alpha[2] = 3.0 / 8.0;
+  p->rk_alpha[3] = 1.0 / 2.0;
+  p->rk_alpha[4] = 1.0;
+  p->n_stages = 5;
+  p->precision = JZ_FP64;
+  return JZ_OK;
+}
+
+size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
+  if (ni < 1 || nj < 1 || nk < 1) return 0;
+  std::string why;
+  jz_params d;
+  if (!p) {
+    jz_params_default(&d);
+    p = &d;
+  }
+  if (!params_ok(p, &why)) return 0;
+  Tiling t;
+  pick_tiling(ni, nj, nk, p, &t);
+  return layout_for((long long)ni * nj * nk, t).total;
+}
+
+int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+              jz_solver** out) {
+  if (!out) return fail(JZ_EINVAL, "jz_create: out is NULL");
+  *out = nullptr;
+  if (ni < 1 || nj < 1 || nk < 1) return fail(JZ_EINVAL, "jz_create: sizes must be >= 1 (got %d %d %d)", ni, nj, nk);
+  if ((long long)ni * nj > (1LL << 30) || (long long)ni * nj * nk > (1LL << 36))
+    return fail(JZ_EINVAL, "jz_create: block too large");
+  std::string why;
+  if (!params_ok(p, &why)) return fail(JZ_EINVAL, "jz_create: %s", why.c_str());
+  jz_solver* s = new jz_solver();
+  s->ni = ni;
+  s->nj = nj;
+  s->nk = nk;
+  s->N = (long long)ni * nj * nk;
+  s->p = *p;
+  s->ph = make_phys(*p);
+  pick_tiling(ni, nj, nk, p, &s->tl);
+  s->L = layout_for(s->N, s->tl);
+  s->stream = (hipStream_t)hip_stream;
+  s->timing = false;
+  s->stage_ms_acc = 0;
+  s->stage_launches_acc = 0;
+  s->stage_bytes_acc = 0;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(JZ_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  if (dev_workspace) {
+    if (ws_bytes < s->L.total) {
+      delete s;
+      return fail(JZ_EINVAL, "jz_create: workspace of %zu bytes < %zu needed", ws_bytes, s->L.total);
+    }
+    if (((uintptr_t)dev_workspace) % kAlign) {
+      delete s;
+      return fail(JZ_EINVAL, "jz_create: workspace must be %zu-byte aligned", kAlign);
+    }
+    s->ws = (char*)dev_workspace;
+    s->owns_ws = false;
+  } else {
+    void* ptr = nullptr;
+    e = hipMalloc(&ptr, s->L.total);
+    if (e != hipSuccess) {
+      delete s;
+      return fail(JZ_ENOMEM, "hipMalloc(%zu): %s", s->L.total, hipGetErrorString(e));
+    }
+    s->ws = (char*)ptr;
+    s->owns_ws = true;
+  }
+  s->q0 = (double*)(s->ws + s->L.q0);
+  s->qa = (double*)(s->ws + s->L.qa);
+  s->qb = (double*)(s->ws + s->L.qb);
+  s->met = (double*)(s->ws + s->L.met);
+  s->norm_part = (double*)(s->ws + s->L.norm_part);
+  s->lam_part = (double*)(s->ws + s->L.lam_part);
+  s->clock = (Clock*)(s->ws + s->L.clock);
+  s->flag = (int*)(s->ws + s->L.flag);
+  s->grid_set = s->state_set = s->dt_valid = false;
+  Clock c0;
+  std::memset(&c0, 0, sizeof c0);
+  int z[4] = {0, 0, 0, 0};
+  e = hipMemcpyAsync(s->clock, &c0, sizeof c0, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->flag, z, sizeof z, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    if (s->owns_ws) (void)hipFree(s->ws);
+    delete s;
+    return fail(JZ_EHIP, "jz_create: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return JZ_OK;
+}
+
+static int read_flag(jz_solver* s, int* f) {
+  HIP_TRY(hipMemcpyAsync(f, s->flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return JZ_OK;
+}
+
+static int clear_flag(jz_solver* s) {
+  const int z = 0;
+  HIP_TRY(hipMemcpyAsync(s->flag, &z, sizeof z, hipMemcpyHostToDevice, s->stream));
+  return JZ_OK;
+}
+
+static int validate_metrics(jz_solver* s, const char* who) {
+  int rc = clear_flag(s);
+  if (rc) return rc;
+  HIP_TRY(launch_check_metrics(s->met, s->N, s->flag, s->stream));
+  int f = 0;
+  rc = read_flag(s, &f);
+  if (rc) return rc;
+  if (f) {
+    s->grid_set = false;
+    clear_flag(s);
+    return fail(JZ_EINVAL, "%s: metric set has %s", who, (f & 1) ? "non-finite values" : "non-positive J");
+  }
+  s->grid_set = true;
+  s->dt_valid = false;
+  return JZ_OK;
+}
+
+int jz_set_grid_coords(jz_solver* s, const double* x, const double* y, const double* z, const double* period) {
+  if (!s || !x || !y || !z || !period) return fail(JZ_EINVAL, "jz_set_grid_coords: NULL argument");
+  const size_t bytes = s->N * sizeof(double);
+  // the coordinates are staged in the (free between steps) stage buffer qa
+  HIP_TRY(hipMemcpyAsync(s->qa, x, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->qa + s->N, y, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->qa + 2 * s->N, z, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(launch_metrics_tl(s->qa, period, s->ni, s->nj, s->nk, s->met, s->stream));
+  return validate_metrics(s, "jz_set_grid_coords");
+}
+
+int jz_set_grid_metrics(jz_solver* s, const double* m, int on_device) {
+  if (!s || !m) return fail(JZ_EINVAL, "jz_set_grid_metrics: NULL argument");
+  HIP_TRY(hipMemcpyAsync(s->met, m, 10 * s->N * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+  return validate_metrics(s, "jz_set_grid_metrics");
+}
+
+int jz_get_grid_metrics(jz_solver* s, double* m, int on_device) {
+  if (!s || !m) return fail(JZ_EINVAL, "jz_get_grid_metrics: NULL argument");
+  if (!s->grid_set) return fail(JZ_ESTATE, "jz_get_grid_metrics: no grid set");
+  HIP_TRY(hipMemcpyAsync(m, s->met, 10 * s->N * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return JZ_OK;
+}
+
+int jz_set_state(jz_solver* s, const double* q, int on_device) {
+  if (!s || !q) return fail(JZ_EINVAL, "jz_set_state: NULL argument");
+  // validate in the stage buffer first so that a bad state leaves Q untouched
+  HIP_TRY(hipMemcpyAsync(s->qa, q, 5 * s->N * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+  int rc = clear_flag(s);
+  if (rc) return rc;
+  HIP_TRY(launch_check_state(s->qa, s->N, s->ph.gm1, s->flag, s->stream));
+  int f = 0;
+  rc = read_flag(s, &f);
+  if (rc) return rc;
+  if (f) {
+    clear_flag(s);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (f & 1) return fail(JZ_ENONFINITE, "jz_set_state: state holds NaN/Inf");
+    return fail(JZ_EINVAL, "jz_set_state: rho or p not positive somewhere");
+  }
+  HIP_TRY(hipMemcpyAsync(s->q0, s->qa, 5 * s->N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->state_set = true;
+  s->dt_valid = false;
+  return JZ_OK;
+}
+
+static StageArgs stage_args(jz_solver* s, const double* qin, double* qout, double alpha) {
+  StageArgs a;
+  a.qin = qin;
+  a.q0 = s->q0;
+  a.qout = qout;
+  a.met = s->met;
+  a.clock = s->clock;
+  a.norm_part = s->norm_part;
+  a.lam_part = s->lam_part;
+  a.alpha = alpha;
+  a.N = s->N;
+  a.ni = s->ni;
+  a.nj = s->nj;
+  a.nk = s->nk;
+  a.tiles_i = s->tl.tiles_i;
+  a.tiles_j = s->tl.tiles_j;
+  a.kchunk = s->tl.kchunk;
+  a.nchunks = s->tl.nchunks;
+  a.ph = s->ph;
+  return a;
+}
+
+static StepCtl step_ctl(jz_solver* s) {
+  StepCtl c;
+  c.cfl = s->p.cfl;
+  c.dt_fixed = s->p.dt_fixed;
+  c.inv_n = 1.0 / (double)s->N;
+  return c;
+}
+
+static int ensure_dt(jz_solver* s) {
+  if (s->dt_valid) return JZ_OK;
+  HIP_TRY(launch_lambda_max(s->q0, s->met, s->N, s->p.gamma, s->lam_part, s->stream));
+  HIP_TRY(launch_finalize_dt(s->clock, s->lam_part, lambda_max_blocks(s->N), step_ctl(s), s->flag, s->stream));
+  s->dt_valid = true;
+  return JZ_OK;
+}
+
+// algorithmic HBM bytes of one stage launch: every array read or written once
+static double stage_bytes(jz_solver* s, int stage) {
+  const double n = (double)s->N;
+  if (stage == 0) return n * (40.0 + 80.0 + 40.0);  // Q^n (which is also Q0), metrics, Q(1)
+  return n * (40.0 + 40.0 + 80.0 + 40.0);           // Q(k-1), Q0, metrics, Q(k)
+}
+
+int jz_advance(jz_solver* s, int nsteps) {
+  if (!s) return fail(JZ_EINVAL, "jz_advance: NULL solver");
+  if (nsteps < 0) return fail(JZ_EINVAL, "jz_advance: nsteps < 0");
+  if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_advance: grid and state must be set first");
+  int rc = ensure_dt(s);
+  if (rc) return rc;
+  const int ns = s->p.n_stages;
+  for (int step = 0; step < nsteps; ++step) {
+    // buffer rotation: Q0 -> Qa -> Qb -> Qa -> Qb -> Q0 (last stage in place:
+    // Q(0) is read only at the node being written)
+    const double* in = s->q0;
+    for (int k = 0; k < ns; ++k) {
+      const bool last = (k == ns - 1);
+      double* out = last ? s->q0 : ((k % 2 == 0) ? s->qa : s->qb);
+      int mode = 0;
+      if (k == 0) mode |= 1;
+      if (last) mode |= 2;
+      StageArgs a = stage_args(s, in, out, s->p.rk_alpha[k]);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (s->timing) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s->stream));
+      }
+      HIP_TRY(launch_stage_fp64(a, s->flag, mode, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream));
+      if (s->timing) {
+        HIP_TRY(hipEventRecord(e1, s->stream));
+        s->ev.emplace_back(e0, e1);
+        s->ev_bytes.push_back(stage_bytes(s, k));
+      }
+      in = out;
+    }
+    HIP_TRY(launch_finalize_step(s->clock, s->norm_part, s->lam_part, s->tl.nblocks, step_ctl(s), s->flag,
+                                 s->stream));
+  }
+  return JZ_OK;
+}
+
+static int check_health(jz_solver* s) {
+  int f = 0;
+  int rc = read_flag(s, &f);
+  if (rc) return rc;
+  if (f) return fail(JZ_ENONFINITE, "a step produced NaN/Inf norms or a non-positive dt");
+  return JZ_OK;
+}
+
+int jz_get_state(jz_solver* s, double* q, int on_device) {
+  if (!s || !q) return fail(JZ_EINVAL, "jz_get_state: NULL argument");
+  if (!s->state_set) return fail(JZ_ESTATE, "jz_get_state: no state set");
+  HIP_TRY(hipMemcpyAsync(q, s->q0, 5 * s->N * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  return check_health(s);
+}
+
+int jz_get_residual_norms(jz_solver* s, double rms[5], double linf[5]) {
+  if (!s || !rms || !linf) return fail(JZ_EINVAL, "jz_get_residual_norms: NULL argument");
+  Clock c;
+  HIP_TRY(hipMemcpyAsync(&c, s->clock, sizeof c, hipMemcpyDeviceToHost, s->stream));
+  int rc = check_health(s);
+  for (int v = 0; v < 5; ++v) {
+    rms[v] = c.rms[v];
+    linf[v] = c.linf[v];
+  }
+  return rc;
+}
+
+int jz_get_clock(jz_solver* s, double* t, double* next_dt, long long* steps) {
+  if (!s) return fail(JZ_EINVAL, "jz_get_clock: NULL solver");
+  if (s->grid_set && s->state_set) {
+    int rc = ensure_dt(s);
+    if (rc) return rc;
+  }
+  Clock c;
+  HIP_TRY(hipMemcpyAsync(&c, s->clock, sizeof c, hipMemcpyDeviceToHost, s->stream));
+  int rc = check_health(s);
+  if (t) *t = c.t;
+  if (next_dt) *next_dt = c.dt;
+  if (steps) *steps = c.steps;
+  return rc;
+}
+
+int jz_set_clock(jz_solver* s, double t, long long steps) {
+  if (!s) return fail(JZ_EINVAL, "jz_set_clock: NULL solver");
+  Clock c;
+  HIP_TRY(hipMemcpyAsync(&c, s->clock, sizeof c, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  c.t = t;
+  c.steps = steps;
+  HIP_TRY(hipMemcpyAsync(s->clock, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return JZ_OK;
+}
+
+int jz_eval_residual(jz_solver* s, double* r, int on_device) {
+  if (!s || !r) return fail(JZ_EINVAL, "jz_eval_residual: NULL argument");
+  if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_eval_residual: grid and state must be set first");
+  StageArgs a = stage_args(s, s->q0, s->qa, 0.0);
+  HIP_TRY(launch_stage_fp64(a, s->flag, 4, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream));
+  HIP_TRY(hipMemcpyAsync(r, s->qa, 5 * s->N * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  return check_health(s);
+}
+
+int jz_eval_dt(jz_solver* s, double* dt, double* lambda_max) {
+  if (!s || !dt) return fail(JZ_EINVAL, "jz_eval_dt: NULL argument");
+  if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_eval_dt: grid and state must be set first");
+  s->dt_valid = false;
+  int rc = ensure_dt(s);
+  if (rc) return rc;
+  Clock c;
+  HIP_TRY(hipMemcpyAsync(&c, s->clock, sizeof c, hipMemcpyDeviceToHost, s->stream));
+  rc = check_health(s);
+  *dt = c.dt;
+  if (lambda_max) *lambda_max = c.lam_max;
+  return rc;
+}
+
+int jz_set_timing(jz_solver* s, int enable) {
+  if (!s) return fail(JZ_EINVAL, "jz_set_timing: NULL solver");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (auto& pr : s->ev) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  s->ev.clear();
+  s->ev_bytes.clear();
+  s->stage_ms_acc = 0;
+  s->stage_launches_acc = 0;
+  s->stage_bytes_acc = 0;
+  s->timing = enable != 0;
+  return JZ_OK;
+}
+
+int jz_get_timing(jz_solver* s, double* stage_ms, long long* stage_launches, double* stage_bytes_out) {
+  if (!s) return fail(JZ_EINVAL, "jz_get_timing: NULL solver");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (size_t i = 0; i < s->ev.size(); ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->ev[i].first, s->ev[i].second));
+    s->stage_ms_acc += ms;
+    s->stage_launches_acc += 1;
+    s->stage_bytes_acc += s->ev_bytes[i];
+    (void)hipEventDestroy(s->ev[i].first);
+    (void)hipEventDestroy(s->ev[i].second);
+  }
+  s->ev.clear();
+  s->ev_bytes.clear();
+  if (stage_ms) *stage_ms = s->stage_ms_acc;
+  if (stage_launches) *stage_launches = s->stage_launches_acc;
+  if (stage_bytes_out) *stage_bytes_out = s->stage_bytes_acc;
+  return JZ_OK;
+}
+
+int jz_destroy(jz_solver* s) {
+  if (!s) return JZ_OK;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& pr : s->ev) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  if (s->owns_ws) (void)hipFree(s->ws);
+  delete s;
+  return JZ_OK;
+}
+
+const char* jz_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// jz_aux.hip -- metric computation, input validation, CFL reduction and the
+// per-step finalize kernel of the jet-LES library.
+#include "jz_internal.h"
+
+namespace jz {
+
+struct Period {
+  double p[9];  // p[3 d + a]: shift of coordinate a when index d wraps forwards
+};
+
+namespace {
+
+__device__ inline int floor_div(int a, int n) {
+  const int q = a / n;
+  return (a % n != 0 && (a < 0)) ? q - 1 : q;
+}
+
+struct CoordView {
+  const double* X;  // 3 x N coordinates
+  long long N;
+  int n[3];
+  Period P;
+  // coordinate a of logical node (c0, c1, c2), unwrapped across the seams
+  __device__ double at(int a, int c0, int c1, int c2) const {
+    const long long idx = (long long)wrap_index(c0, n[0]) +
+                          (long long)n[0] * (wrap_index(c1, n[1]) + (long long)n[1] * wrap_index(c2, n[2]));
+    double v = X[a * N + idx];
+    v += floor_div(c0, n[0]) * P.p[a];
+    v += floor_div(c1, n[1]) * P.p[3 + a];
+    v += floor_div(c2, n[2]) * P.p[6 + a];
+    return v;
+  }
+  // centred difference of coordinate a along direction d at logical node c
+  __device__ double dd(int a, int d, int c0, int c1, int c2) const {
+    int p[3] = {c0, c1, c2}, m[3] = {c0, c1, c2};
+    p[d] += 1;
+    m[d] -= 1;
+    return 0.5 * (at(a, p[0], p[1], p[2]) - at(a, m[0], m[1], m[2]));
+  }
+};
+
+}  // namespace
+
+// Discretely conservative (Thomas-Lombard) metric set: for cyclic (d, d1, d2)
+// and (a, a1, a2),  S^d_a = delta_d2(X_a2 delta_d1 X_a1) - delta_d1(X_a2 delta_d2 X_a1),
+// with X_a2 measured from the centre node; J = 1 / det(delta_d X_a).  Because
+// the centred differences commute, sum_d delta_d S^d_a vanishes identically,
+// which keeps a uniform flow exactly steady on any grid.
+__global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, double* __restrict__ m) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= cv.N) return;
+  const int i = (int)(n % cv.n[0]);
+  const int j = (int)((n / cv.n[0]) % cv.n[1]);
+  const int k = (int)(n / ((long long)cv.n[0] * cv.n[1]));
+  const int c[3] = {i, j, k};
+  for (int d = 0; d < 3; ++d) {
+    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    for (int a = 0; a < 3; ++a) {
+      const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+      const double xc = cv.at(a2, i, j, k);
+      int p[3], q[3];
+      // delta_d2 ( X_a2 delta_d1 X_a1 )
+      for (int e = 0; e < 3; ++e) p[e] = q[e] = c[e];
+      p[d2] += 1;
+      q[d2] -= 1;
+      const double t1 = 0.5 * ((cv.at(a2, p[0], p[1], p[2]) - xc) * cv.dd(a1, d1, p[0], p[1], p[2]) -
+                               (cv.at(a2, q[0], q[1], q[2]) - xc) * cv.dd(a1, d1, q[0], q[1], q[2]));
+      // delta_d1 ( X_a2 delta_d2 X_a1 )
+      for (int e = 0; e < 3; ++e) p[e] = q[e] = c[e];
+      p[d1] += 1;
+      q[d1] -= 1;
+      const double t2 = 0.5 * ((cv.at(a2, p[0], p[1], p[2]) - xc) * cv.dd(a1, d2, p[0], p[1], p[2]) -
+                               (cv.at(a2, q[0], q[1], q[2]) - xc) * cv.dd(a1, d2, q[0], q[1], q[2]));
+      m[(3 * d + a) * cv.N + n] = t1 - t2;
+    }
+  }
+  double M[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) M[a][d] = cv.dd(a, d, i, j, k);
+  const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                     M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                     M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  m[9 * cv.N + n] = 1.0 / det;
+}
+
+// flag |= 1 for a non-finite metric, |= 2 for J <= 0
+__global__ __launch_bounds__(256) void check_metrics_kernel(const double* __restrict__ m, long long N,
+                                                            int* __restrict__ flag) {
+  int bad = 0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    for (int c = 0; c < 10; ++c)
+      if (!isfinite(m[c * N + n])) bad |= 1;
+    if (!(m[9 * N + n] > 0.0)) bad |= 2;
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+// flag |= 1 for a non-finite value, |= 2 for rho <= 0 or p <= 0
+__global__ __launch_bounds__(256) void check_state_kernel(const double* __restrict__ q, long long N, double gm1,
+                                                          int* __restrict__ flag) {
+  int bad = 0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    double v[5];
+    for (int c = 0; c < 5; ++c) {
+      v[c] = q[c * N + n];
+      if (!isfinite(v[c])) bad |= 1;
+    }
+    const double p = gm1 * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
+    if (!(v[0] > 0.0) || !(p > 0.0)) bad |= 2;
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+// per-block max of sum_d lambda^d (grid-stride; max is order-independent)
+__global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restrict__ q, const double* __restrict__ m,
+                                                         long long N, double gamma, double* __restrict__ part) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    double qq[5], mm[10];
+    for (int c = 0; c < 5; ++c) qq[c] = q[c * N + n];
+    for (int c = 0; c < 10; ++c) mm[c] = m[c * N + n];
+    mx = max_nan(mx, lambda_sum(qq, mm, gamma));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = max_nan(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+namespace {
+constexpr int FIN_T = 256;
+
+// Fixed-order reduction of nb partials: thread t folds b = t, t+256, ... in
+// order, then a fixed binary tree.  Bitwise reproducible for a given nb.
+__device__ double block_sum(const double* part, int stride, int nb, double* red) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += FIN_T) acc += part[(long long)b * stride];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = FIN_T / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(const double* part, int stride, int nb, double* red) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += FIN_T) acc = max_nan(acc, part[(long long)b * stride]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = FIN_T / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = max_nan(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double dt_rule(const StepCtl& c, double lmax) { return c.dt_fixed > 0.0 ? c.dt_fixed : c.cfl / lmax; }
+}  // namespace
+
+// dt of the first step after a new state: from the lambda partials only
+__global__ __launch_bounds__(FIN_T) void finalize_dt_kernel(Clock* clk, const double* __restrict__ lam_part, int nb,
+                                                            StepCtl ctl, int* __restrict__ flag) {
+  __shared__ double red[FIN_T];
+  const double lmax = block_max(lam_part, 1, nb, red);
+  if (threadIdx.x == 0) {
+    const double dt = dt_rule(ctl, lmax);
+    clk->lam_max = lmax;
+    clk->dt = dt;
+    if (!isfinite(lmax) || !isfinite(dt) || !(dt > 0.0)) *flag |= 1;
+  }
+}
+
+// end of a step: advance the clock by the dt just used, store the first-stage
+// norms, and set the next dt from the last stage's lambda partials
+__global__ __launch_bounds__(FIN_T) void finalize_step_kernel(Clock* clk, const double* __restrict__ norm_part,
+                                                              const double* __restrict__ lam_part, int nb,
+                                                              StepCtl ctl, int* __restrict__ flag) {
+  __shared__ double red[FIN_T];
+  if (*flag) return;
+  double sums[5], maxs[5];
+  for (int v = 0; v < 5; ++v) {
+    sums[v] = block_sum(norm_part + v, 10, nb, red);
+    maxs[v] = block_max(norm_part + 5 + v, 10, nb, red);
+  }
+  const double lmax = block_max(lam_part, 1, nb, red);
+  if (threadIdx.x == 0) {
+    bool ok = true;
+    for (int v = 0; v < 5; ++v) {
+      clk->rms[v] = sqrt(sums[v] * ctl.inv_n);
+      clk->linf[v] = maxs[v];
+      ok = ok && isfinite(sums[v]) && isfinite(maxs[v]);
+    }
+    clk->t += clk->dt;
+    clk->steps += 1;
+    const double dt = dt_rule(ctl, lmax);
+    clk->lam_max = lmax;
+    clk->dt = dt;
+    ok = ok && isfinite(lmax) && isfinite(dt) && dt > 0.0;
+    if (!ok) *flag |= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, double* m,
+                             hipStream_t st) {
+  CoordView cv;
+  cv.X = X;
+  cv.N = (long long)ni * nj * nk;
+  cv.n[0] = ni;
+  cv.n[1] = nj;
+  cv.n[2] = nk;
+  for (int c = 0; c < 9; ++c) cv.P.p[c] = period9[c];
+  const long long nb = (cv.N + 255) / 256;
+  hipLaunchKernelGGL(metrics_tl_kernel, dim3((unsigned)nb), dim3(256), 0, st, cv, m);
+  return hipGetLastError();
+}
+
+static unsigned grid_stride_blocks(long long N) {
+  long long nb = (N + 255) / 256;
+  return (unsigned)(nb < 2048 ? (nb < 1 ? 1 : nb) : 2048);
+}
+
+hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(check_metrics_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m, N, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(check_state_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, N, gm1, flag);
+  return hipGetLastError();
+}
+
+int lambda_max_blocks(long long N) { return (int)grid_stride_blocks(N); }
+
+hipError_t launch_lambda_max(const double* q, const double* m, long long N, double gamma, double* part,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(lambda_max_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, m, N, gamma, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCtl ctl, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(FIN_T), 0, st, clk, lam_part, nb, ctl, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
+                                int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_step_kernel, dim3(1), dim3(FIN_T), 0, st, clk, norm_part, lam_part, nb, ctl, flag);
+  return hipGetLastError();
+}
+
+}  // namespace jz

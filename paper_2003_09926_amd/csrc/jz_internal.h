@@ -1,0 +1,103 @@
+// jz_internal.h -- device-side declarations shared by the HIP sources of the
+// jet-LES library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jz {
+
+// Physical constants of one block, derived once on the host from jz_params.
+struct Phys {
+  double gamma;       // ratio of specific heats
+  double gm1;         // gamma - 1
+  double mu_suth;     // mu_inf (1 + S): Sutherland numerator with T_inf = 1
+  double suth_s;      // S
+  double cs2;         // Cs^2
+  double kap_lam;     // Cp / Pr
+  double kap_turb;    // Cp / Pr_t
+  double k2, k4;      // dissipation coefficients
+  double tv_alpha;    // anisotropic scaling exponent
+  int alpha_half;     // tv_alpha == 0.5 (square-root fast path)
+  int pad;
+};
+
+// Device-resident clock and diagnostics of one solver (lives in the workspace).
+struct Clock {
+  double t;          // simulated time
+  double dt;         // step size of the next (or current) step
+  double lam_max;    // max over nodes of sum_d lambda^d behind dt
+  double rms[5];     // first-stage residual norms of the last step
+  double linf[5];
+  long long steps;
+  int flag;          // 0 = healthy; bit 0: non-finite; bit 1: non-positive rho/p/J
+  int pad;
+};
+
+// Per-step reduction settings read by the finalize kernels.
+struct StepCtl {
+  double cfl;
+  double dt_fixed;
+  double inv_n;       // 1 / N
+};
+
+// Launch shape of the fused stage kernel.
+struct Tiling {
+  int bx, by;         // workgroup = bx x by threads covering the tile and its 2-node halo
+  int ti, tj;         // owned tile = (bx - 4) x (by - 4)
+  int kchunk;         // planes marched per workgroup
+  int tiles_i, tiles_j, nchunks;
+  int nblocks;
+};
+
+struct StageArgs {
+  const double* qin;    // stencil input Q(k-1), 5 x N
+  const double* q0;     // Q(0), 5 x N (read at the owned node only)
+  double* qout;         // Q(k) (or R in residual mode), 5 x N
+  const double* met;    // 10 x N
+  const Clock* clock;   // dt
+  double* norm_part;    // [nblocks][10] first-stage partial sums / maxima
+  double* lam_part;     // [nblocks] max sum_d lambda^d of the updated state
+  double alpha;         // stage coefficient
+  long long N;
+  int ni, nj, nk;
+  int tiles_i, tiles_j, kchunk, nchunks;
+  Phys ph;
+};
+
+__host__ __device__ inline int wrap_index(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// NaN-propagating maximum (a plain fmax would drop a NaN).
+__device__ inline double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// sum_d lambda^d at one node: |J S^d . u| + a J |S^d|, the inviscid spectral
+// radii in index units that set the CFL time step.
+__device__ inline double lambda_sum(const double q[5], const double m[10], double gamma) {
+  const double rinv = 1.0 / q[0];
+  const double u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
+  const double p = (gamma - 1.0) * (q[4] - 0.5 * q[0] * (u * u + v * v + w * w));
+  const double a = sqrt(gamma * p * rinv);
+  const double J = m[9];
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double sx = m[3 * d], sy = m[3 * d + 1], sz = m[3 * d + 2];
+    s += fabs(J * (sx * u + sy * v + sz * w)) + a * J * sqrt(sx * sx + sy * sy + sz * sz);
+  }
+  return s;
+}
+
+// Block index -> logical tile, so that the consecutive logical tiles (which
+// share halo rows) land on the same XCD and its L2.  Workgroups are dispatched
+// round-robin over the 8 XCDs of an MI355X.
+__device__ inline int xcd_remap(int b, int nb) {
+  constexpr int NX = 8;
+  const int q = nb / NX, r = nb % NX;
+  const int x = b % NX;
+  return x * q + (x < r ? x : r) + b / NX;
+}
+
+}  // namespace jz
