@@ -126,7 +126,20 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="instead of the workload, run 5 plain device copies of MIB MiB "
+                         "(reference kernel for the HBM byte counters)")
     a = ap.parse_args(argv)
+    if a.copy_calibrate:
+        import torch
+        n = a.copy_calibrate * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibrate_bytes_each_way": n * 8, "copies": 5}), flush=True)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs one GPU per process and measures one GPU; "
                                    "--gpus above 1 is not supported"}), flush=True)
