@@ -16,6 +16,8 @@ hipError_t launch_stage_fp64(const StageArgs& a, const int* flag, int mode, int 
 bool stage_shape_supported(int bx, int by);
 hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, double* m,
                              hipStream_t st);
+hipError_t launch_soa_to_nodes(const double* src, double* dst, long long N, int C, hipStream_t st);
+hipError_t launch_nodes_to_soa(const double* src, double* dst, long long N, int C, hipStream_t st);
 hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st);
 hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st);
 int lambda_max_blocks(long long N);
@@ -52,8 +54,12 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Device workspace.  Q0, Qa, Qb and the metrics are node-major (5 resp. 10
+// doubles per node).  Qa and Qb are contiguous (each 5 x Np doubles, Np = N
+// rounded up to 32) so that together they can stage a 10 x N metric set.
 struct Layout {
   size_t q0, qa, qb, met, norm_part, lam_part, clock, flag, total;
+  long long np;
 };
 
 void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
@@ -82,9 +88,10 @@ Layout layout_for(long long N, const Tiling& t) {
     off = align_up(off + bytes);
     return o;
   };
+  L.np = (N + 31) / 32 * 32;
   L.q0 = take(5 * N * sizeof(double));
-  L.qa = take(5 * N * sizeof(double));
-  L.qb = take(5 * N * sizeof(double));
+  L.qa = take(10 * L.np * sizeof(double));
+  L.qb = L.qa + 5 * L.np * sizeof(double);
   L.met = take(10 * N * sizeof(double));
   L.norm_part = take((size_t)t.nblocks * 10 * sizeof(double));
   const int lb = t.nblocks > lambda_max_blocks(N) ? t.nblocks : lambda_max_blocks(N);
@@ -335,15 +342,18 @@ int jz_set_grid_coords(jz_solver* s, const double* x, const double* y, const dou
 
 int jz_set_grid_metrics(jz_solver* s, const double* m, int on_device) {
   if (!s || !m) return fail(JZ_EINVAL, "jz_set_grid_metrics: NULL argument");
-  HIP_TRY(hipMemcpyAsync(s->met, m, 10 * s->N * sizeof(double),
+  // stage the 10 x N array in Qa|Qb, then transpose to the node-major layout
+  HIP_TRY(hipMemcpyAsync(s->qa, m, 10 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(launch_soa_to_nodes(s->qa, s->met, s->N, 10, s->stream));
   return validate_metrics(s, "jz_set_grid_metrics");
 }
 
 int jz_get_grid_metrics(jz_solver* s, double* m, int on_device) {
   if (!s || !m) return fail(JZ_EINVAL, "jz_get_grid_metrics: NULL argument");
   if (!s->grid_set) return fail(JZ_ESTATE, "jz_get_grid_metrics: no grid set");
-  HIP_TRY(hipMemcpyAsync(m, s->met, 10 * s->N * sizeof(double),
+  HIP_TRY(launch_nodes_to_soa(s->met, s->qa, s->N, 10, s->stream));
+  HIP_TRY(hipMemcpyAsync(m, s->qa, 10 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return JZ_OK;
@@ -351,9 +361,10 @@ int jz_get_grid_metrics(jz_solver* s, double* m, int on_device) {
 
 int jz_set_state(jz_solver* s, const double* q, int on_device) {
   if (!s || !q) return fail(JZ_EINVAL, "jz_set_state: NULL argument");
-  // validate in the stage buffer first so that a bad state leaves Q untouched
-  HIP_TRY(hipMemcpyAsync(s->qa, q, 5 * s->N * sizeof(double),
+  // validate a node-major copy in Qa first so that a bad state leaves Q untouched
+  HIP_TRY(hipMemcpyAsync(s->qb, q, 5 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(launch_soa_to_nodes(s->qb, s->qa, s->N, 5, s->stream));
   int rc = clear_flag(s);
   if (rc) return rc;
   HIP_TRY(launch_check_state(s->qa, s->N, s->ph.gm1, s->flag, s->stream));
@@ -467,7 +478,8 @@ static int check_health(jz_solver* s) {
 int jz_get_state(jz_solver* s, double* q, int on_device) {
   if (!s || !q) return fail(JZ_EINVAL, "jz_get_state: NULL argument");
   if (!s->state_set) return fail(JZ_ESTATE, "jz_get_state: no state set");
-  HIP_TRY(hipMemcpyAsync(q, s->q0, 5 * s->N * sizeof(double),
+  HIP_TRY(launch_nodes_to_soa(s->q0, s->qa, s->N, 5, s->stream));
+  HIP_TRY(hipMemcpyAsync(q, s->qa, 5 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
   return check_health(s);
 }
@@ -516,7 +528,8 @@ int jz_eval_residual(jz_solver* s, double* r, int on_device) {
   if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_eval_residual: grid and state must be set first");
   StageArgs a = stage_args(s, s->q0, s->qa, 0.0);
   HIP_TRY(launch_stage_fp64(a, s->flag, 4, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream));
-  HIP_TRY(hipMemcpyAsync(r, s->qa, 5 * s->N * sizeof(double),
+  HIP_TRY(launch_nodes_to_soa(s->qa, s->qb, s->N, 5, s->stream));
+  HIP_TRY(hipMemcpyAsync(r, s->qb, 5 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
   return check_health(s);
 }

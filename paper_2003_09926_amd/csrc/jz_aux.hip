@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, double* _
       q[d1] -= 1;
       const double t2 = 0.5 * ((cv.at(a2, p[0], p[1], p[2]) - xc) * cv.dd(a1, d2, p[0], p[1], p[2]) -
                                (cv.at(a2, q[0], q[1], q[2]) - xc) * cv.dd(a1, d2, q[0], q[1], q[2]));
-      m[(3 * d + a) * cv.N + n] = t1 - t2;
+      m[10 * n + 3 * d + a] = t1 - t2;
     }
   }
   double M[3][3];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, double* _
   const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
                      M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
                      M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-  m[9 * cv.N + n] = 1.0 / det;
+  m[10 * n + 9] = 1.0 / det;
 }
 
 // flag |= 1 for a non-finite metric, |= 2 for J <= 0
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(256) void check_metrics_kernel(const double* __rest
   int bad = 0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
     for (int c = 0; c < 10; ++c)
-      if (!isfinite(m[c * N + n])) bad |= 1;
-    if (!(m[9 * N + n] > 0.0)) bad |= 2;
+      if (!isfinite(m[10 * n + c])) bad |= 1;
+    if (!(m[10 * n + 9] > 0.0)) bad |= 2;
   }
   if (bad) atomicOr(flag, bad);
 }
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void check_state_kernel(const double* __restri
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
     double v[5];
     for (int c = 0; c < 5; ++c) {
-      v[c] = q[c * N + n];
+      v[c] = q[5 * n + c];
       if (!isfinite(v[c])) bad |= 1;
     }
     const double p = gm1 * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
@@ -118,8 +118,8 @@ __global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restric
   double mx = 0.0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
     double qq[5], mm[10];
-    for (int c = 0; c < 5; ++c) qq[c] = q[c * N + n];
-    for (int c = 0; c < 10; ++c) mm[c] = m[c * N + n];
+    for (int c = 0; c < 5; ++c) qq[c] = q[5 * n + c];
+    for (int c = 0; c < 10; ++c) mm[c] = m[10 * n + c];
     mx = max_nan(mx, lambda_sum(qq, mm, gamma));
   }
   red[threadIdx.x] = mx;
@@ -210,6 +210,20 @@ __global__ __launch_bounds__(FIN_T) void finalize_step_kernel(Clock* clk, const 
   }
 }
 
+// structure-of-arrays (c x N, the ABI layout) <-> node-major (N x c, the
+// library's internal layout)
+__global__ __launch_bounds__(256) void soa_to_nodes_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                           long long N, int C) {
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x)
+    for (int c = 0; c < C; ++c) dst[C * n + c] = src[c * N + n];
+}
+
+__global__ __launch_bounds__(256) void nodes_to_soa_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                           long long N, int C) {
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x)
+    for (int c = 0; c < C; ++c) dst[c * N + n] = src[C * n + c];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -239,6 +253,16 @@ hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStre
 
 hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(check_state_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, N, gm1, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_soa_to_nodes(const double* src, double* dst, long long N, int C, hipStream_t st) {
+  hipLaunchKernelGGL(soa_to_nodes_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, src, dst, N, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_nodes_to_soa(const double* src, double* dst, long long N, int C, hipStream_t st) {
+  hipLaunchKernelGGL(nodes_to_soa_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, src, dst, N, C);
   return hipGetLastError();
 }
 

@@ -26,7 +26,10 @@
 //     gets its fluxes, and plane s gets its residual and is written.
 // Every global access uses periodically wrapped indices, so the halo is the
 // block's own periodic image (standing in for the neighbour-rank ghost
-// layers of Sec. 4.3).
+// layers of Sec. 4.3).  Inside the library Q is stored node-major (the five
+// conserved variables of a node contiguous, 40 B) and the metric set likewise
+// (10 doubles, 80 B per node): one address per node and array, and a
+// wavefront still reads one contiguous span per plane row.
 #include "jz_internal.h"
 
 namespace jz {
@@ -105,7 +108,6 @@ __global__ __launch_bounds__(BX* BY) void stage_fp64(StageArgs A, const int* __r
   const int ui = i0 - 2 + tx, uj = j0 - 2 + ty;  // unwrapped column indices
   const long long col = (long long)wrap_index(ui, A.ni) + (long long)A.ni * wrap_index(uj, A.nj);
   const long long plane = (long long)A.ni * A.nj;
-  const long long N = A.N;
   const bool isG = (tx >= 1 && tx < BX - 1 && ty >= 1 && ty < BY - 1);
   const bool isI = (tx >= 2 && tx < BX - 2 && ty >= 2 && ty < BY - 2 && ui < A.ni && uj < A.nj);
 
@@ -131,26 +133,37 @@ __global__ __launch_bounds__(BX* BY) void stage_fp64(StageArgs A, const int* __r
   double nsum[5] = {0, 0, 0, 0, 0}, nmax[5] = {0, 0, 0, 0, 0};
   double lmax = 0.0;
 
+  // software prefetch, one march step ahead: Q of the next lead plane and
+  // the metrics of the next gradient plane
+  double Qn[5], Mn[10];
+
   // ring slots: plane k lives in slot (k - kbeg + 3) % 3
   int slot_s = 1, slot_g = 2, slot_l = 0;  // planes kbeg-2, kbeg-1, kbeg
   {
-    const long long n0 = node(kbeg - 2), n1 = node(kbeg - 1);
+    const long long n0 = node(kbeg - 2), n1 = node(kbeg - 1), n2 = node(kbeg);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      Qs[v] = qin[v * N + n0];
-      Qg[v] = qin[v * N + n1];
+      Qs[v] = qin[5 * n0 + v];
+      Qg[v] = qin[5 * n1 + v];
+      Qn[v] = qin[5 * n2 + v];
       Qm[v] = 0.0;
+    }
+    if (isG) {
+#pragma unroll
+      for (int c = 0; c < 10; ++c) Mn[c] = met[10 * n1 + c];
     }
     put_prims(slot_s, Qs);
     put_prims(slot_g, Qg);
   }
 
   for (int s = kbeg - 2; s < kend; ++s) {
-    // ---- lead plane s+2: load (own column) ---------------------------------
-    {
-      const long long nl = node(s + 2);
+    // ---- lead plane s+2 (prefetched); prefetch plane s+3 -------------------
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Ql[v] = qin[v * N + nl];
+    for (int v = 0; v < 5; ++v) Ql[v] = Qn[v];
+    if (s + 3 < kend + 2) {
+      const long long nn = node(s + 3);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Qn[v] = qin[5 * nn + v];
     }
     __syncthreads();  // the previous step's readers of slot_l, sQ, sF*, sS*, sN* are done
     put_prims(slot_l, Ql);
@@ -161,10 +174,14 @@ __global__ __launch_bounds__(BX* BY) void stage_fp64(StageArgs A, const int* __r
     // ---- gradient plane g = s+1: fluxes, dissipation scales, sensors ------
     double Fzg[5] = {0, 0, 0, 0, 0}, sigg = 0.0, nug = 0.0, Jg = 0.0;
     if (isG) {
-      const long long ng = node(s + 1);
       double m[10];
 #pragma unroll
-      for (int c = 0; c < 10; ++c) m[c] = met[c * N + ng];
+      for (int c = 0; c < 10; ++c) m[c] = Mn[c];
+      if (s + 2 < kend + 1) {
+        const long long nm = node(s + 2);
+#pragma unroll
+        for (int c = 0; c < 10; ++c) Mn[c] = met[10 * nm + c];
+      }
       const double J = m[9];
       Jg = J;
       const double (*Pg)[NT] = sPr[slot_g];
@@ -267,7 +284,7 @@ __global__ __launch_bounds__(BX* BY) void stage_fp64(StageArgs A, const int* __r
         const double e2ym = ph.k2 * fmax(sNy[t - BX], sNy[t]);
         const double e4yp = fmax(0.0, ph.k4 - e2yp), e4ym = fmax(0.0, ph.k4 - e2ym);
         const double sgyp = 0.5 * (sSy[t] + sSy[t + BX]), sgym = 0.5 * (sSy[t - BX] + sSy[t]);
-#pragma unroll
+#pragma unroll 1
         for (int v = 0; v < 5; ++v) {
           const double q0 = sQ[v][t];
           const double qxp = sQ[v][t + 1], qxpp = sQ[v][t + 2], qxm = sQ[v][t - 1], qxmm = sQ[v][t - 2];
@@ -299,18 +316,18 @@ __global__ __launch_bounds__(BX* BY) void stage_fp64(StageArgs A, const int* __r
           for (int v = 0; v < 5; ++v) R[v] = Js * (Rin[v] + (Hp[v] - Hm[v]));
           if (WRITE_R) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) A.qout[v * N + ns] = R[v];
+            for (int v = 0; v < 5; ++v) A.qout[5 * ns + v] = R[v];
           } else {
             double qn[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-              qn[v] = A.q0[v * N + ns] - adt * R[v];
-              A.qout[v * N + ns] = qn[v];
+              qn[v] = A.q0[5 * ns + v] - adt * R[v];
+              A.qout[5 * ns + v] = qn[v];
             }
             if (LAMMAX) {
               double m[10];
 #pragma unroll
-              for (int c = 0; c < 10; ++c) m[c] = met[c * N + ns];
+              for (int c = 0; c < 10; ++c) m[c] = met[10 * ns + c];
               lmax = max_nan(lmax, lambda_sum(qn, m, ph.gamma));
             }
           }
