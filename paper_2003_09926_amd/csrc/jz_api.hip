@@ -73,7 +73,7 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   t->tj = t->by - 4;
   t->tiles_i = (ni + t->ti - 1) / t->ti;
   t->tiles_j = (nj + t->tj - 1) / t->tj;
-  int kc = (p && p->kchunk > 0) ? p->kchunk : 32;
+  int kc = (p && p->kchunk > 0) ? p->kchunk : 64;
   if (kc > nk) kc = nk;
   t->kchunk = kc;
   t->nchunks = (nk + kc - 1) / kc;
