@@ -31,7 +31,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def _kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("jz_stage.hip", "jz_internal.h"):
+    for f in ("jz_stage_kernel.h", "jz_stage.hip", "jz_stage32.hip", "jz_internal.h"):
         with open(os.path.join(ROOT, "paper_2003_09926_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,14 +72,40 @@ def cpu_baseline(min_seconds: float = 10.0):
                       f"stretched jet grid (FP64 C++ oracle, OpenMP), {el:.1f} s"}
 
 
-def run_fp64(steps: int, warmup: int, with_cpu: bool):
+def fp32_error_vs_oracle():
+    """Config-3 error: the FP32-flux form against the FP64 oracle on the
+    128 x 64 x 64 stride-4 subsample after 1 and 100 steps (relative L2 per
+    conserved variable)."""
+    import numpy as np
+    import oracle
+    from paper_2003_09926_amd import binding as B
+    from paper_2003_09926_amd import inputs as I
+    g, q = I.stretched_jet_case(DIMS, seed=2, stride=4)
+    P = oracle.default_params(re_d=1.0e6)
+    rel = lambda a, b: [float(np.linalg.norm(a[v] - b[v]) / np.linalg.norm(b[v])) for v in range(5)]
+    with B.Solver(g.dims, B.params_default(re_d=1.0e6, precision=B.JZ_FP32_FLUX)) as s:
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        s.advance(1)
+        g1 = s.get_state()
+        s.advance(99)
+        g100 = s.get_state()
+    o1, _, _, _ = oracle.step(g.dims, P, g.metrics, q)
+    o100, _, _, _ = oracle.advance(g.dims, P, g.metrics, q, 100)
+    names = ["rho", "rho_u", "rho_v", "rho_w", "e"]
+    return {"grid": "128x64x64 stride-4 subsample", "after_1_step": dict(zip(names, rel(g1, o1))),
+            "after_100_steps": dict(zip(names, rel(g100, o100)))}
+
+
+def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bool):
     import torch
     from paper_2003_09926_amd import binding as B
     from paper_2003_09926_amd import inputs as I
 
     torch.cuda.set_device(0)
+    prec = B.JZ_FP64 if form == "fp64" else B.JZ_FP32_FLUX
     g, q = I.stretched_jet_case(DIMS, seed=2)
-    P = B.params_default(re_d=1.0e6)
+    P = B.params_default(re_d=1.0e6, precision=prec)
     s = B.Solver(g.dims, P)
     s.set_grid_metrics(g.metrics)
     s.set_state(q)
@@ -101,19 +127,23 @@ def run_fp64(steps: int, warmup: int, with_cpu: bool):
     avg_ms = stage_ms / max(launches, 1)
     bytes_per_launch = stage_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic("stage_fp64")
+    kernel = "stage_fp64" if form == "fp64" else "stage_fp32flux"
+    traffic = _traffic(kernel)
     out = {
         "metric": "point-stage updates/s", "value": value, "unit": "point-stage updates/s",
         "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": el * 1e3 / steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if form == "fp64" else "f32 (fluxes) + f64 (accumulation, J, norms)",
         "data": "synthetic",
-        "config": {"workload": "jet_512x256x256_stretched_fp64", "dims": list(DIMS), "mach": 1.4,
-                   "re_d": 1.0e6, "seed": 2, "stages_per_step": 5, "form": "fp64"},
+        "config": {"workload": f"jet_512x256x256_stretched_{form}", "dims": list(DIMS), "mach": 1.4,
+                   "re_d": 1.0e6, "seed": 2, "stages_per_step": 5, "form": form},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "stage_fp64", "avg_launch_ms": avg_ms,
+                     "kernel": kernel, "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    if with_error and form == "fp32":
+        out["error_vs_oracle"] = fp32_error_vs_oracle()
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline()
     return out
@@ -124,7 +154,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="fp64", choices=["fp64"])
+    ap.add_argument("--form", default="fp64", choices=["fp64", "fp32"],
+                    help="fp64: FP64 path (default); fp32: FP32-flux form on the same workload")
+    ap.add_argument("--no-error", action="store_true", help="fp32 form: skip the error-vs-oracle run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB "
@@ -145,7 +177,8 @@ def main(argv=None):
                                    "--gpus above 1 is not supported"}), flush=True)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
-    out = run_fp64(a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu))
+    out = run_block(a.form, a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu),
+                    with_error=not a.no_error)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -13,16 +13,22 @@
 namespace jz {
 hipError_t launch_stage_fp64(const StageArgs& a, const int* flag, int mode, int bx, int by, int nblocks,
                              hipStream_t st);
-bool stage_shape_supported(int bx, int by);
-hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, double* m,
+hipError_t launch_stage_fp32(const StageArgs& a, const int* flag, int kind, int bx, int by, int nblocks,
                              hipStream_t st);
+bool stage_shape_supported(int bx, int by);
+bool stage32_shape_supported(int bx, int by);
+hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst, long long N, hipStream_t st);
+hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, void* m, double* jac,
+                             bool met32, hipStream_t st);
+hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int* flag, hipStream_t st);
+hipError_t launch_soa_to_met32(const double* src, float* m32, double* jac, long long N, hipStream_t st);
 hipError_t launch_soa_to_nodes(const double* src, double* dst, long long N, int C, hipStream_t st);
 hipError_t launch_nodes_to_soa(const double* src, double* dst, long long N, int C, hipStream_t st);
 hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st);
 hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st);
 int lambda_max_blocks(long long N);
-hipError_t launch_lambda_max(const double* q, const double* m, long long N, double gamma, double* part,
-                             hipStream_t st);
+hipError_t launch_lambda_max(const double* q, const void* met, const double* jac, bool met32, long long N,
+                             double gamma, double* part, hipStream_t st);
 hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCtl ctl, int* flag, hipStream_t st);
 hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
                                 int* flag, hipStream_t st);
@@ -54,17 +60,23 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Device workspace.  Q0, Qa, Qb and the metrics are node-major (5 resp. 10
-// doubles per node).  Qa and Qb are contiguous (each 5 x Np doubles, Np = N
-// rounded up to 32) so that together they can stage a 10 x N metric set.
+// Device workspace.  Q0 and every stage state are node-major (5 values per
+// node).  "stage" is a scratch region of Np-rounded rows (Np = N rounded up to
+// 32): its halves A and B (5 x Np doubles each) are the FP64 stage buffers
+// Qa/Qb, and between steps it stages transposes, coordinates and metrics.
+//   FP64:      Q0 | stage (10 Np doubles) | metrics (10 doubles per node)
+//   FP32-flux: Q0 | stage (10 Np doubles; during a step its first 10 Np
+//              floats are the float stage states Q32a, Q32b) | metrics
+//              (9 floats per node) | J (1 double per node)
 struct Layout {
-  size_t q0, qa, qb, met, norm_part, lam_part, clock, flag, total;
+  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, total;
   long long np;
 };
 
 void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
-  t->bx = 32;
-  t->by = 16;
+  const bool f32 = p && p->precision == JZ_FP32_FLUX;
+  t->bx = f32 ? 32 : 32;
+  t->by = f32 ? 24 : 16;
   if (p && p->tile_i > 0 && p->tile_j > 0) {
     t->bx = p->tile_i + 4;
     t->by = p->tile_j + 4;
@@ -80,8 +92,9 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
 }
 
-Layout layout_for(long long N, const Tiling& t) {
+Layout layout_for(long long N, const Tiling& t, int prec) {
   Layout L;
+  std::memset(&L, 0, sizeof L);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -90,9 +103,15 @@ Layout layout_for(long long N, const Tiling& t) {
   };
   L.np = (N + 31) / 32 * 32;
   L.q0 = take(5 * N * sizeof(double));
-  L.qa = take(10 * L.np * sizeof(double));
-  L.qb = L.qa + 5 * L.np * sizeof(double);
-  L.met = take(10 * N * sizeof(double));
+  L.stage = take(10 * L.np * sizeof(double));
+  if (prec == JZ_FP64) {
+    L.met = take(10 * N * sizeof(double));
+  } else {
+    L.q32a = L.stage;
+    L.q32b = L.stage + 5 * L.np * sizeof(float);
+    L.met = take(9 * N * sizeof(float));
+    L.jac = take(N * sizeof(double));
+  }
   L.norm_part = take((size_t)t.nblocks * 10 * sizeof(double));
   const int lb = t.nblocks > lambda_max_blocks(N) ? t.nblocks : lambda_max_blocks(N);
   L.lam_part = take((size_t)lb * sizeof(double));
@@ -117,16 +136,20 @@ bool params_ok(const jz_params* p, std::string* why) {
     *why = "n_stages must be 1..5";
     return false;
   }
-  if (p->precision != JZ_FP64) {
-    *why = "precision must be JZ_FP64 for a single block";
+  if (p->precision != JZ_FP64 && p->precision != JZ_FP32_FLUX) {
+    *why = "precision must be JZ_FP64 or JZ_FP32_FLUX";
     return false;
   }
   if ((p->tile_i > 0) != (p->tile_j > 0)) {
     *why = "tile_i and tile_j must both be set or both be 0";
     return false;
   }
-  if (p->tile_i > 0 && !stage_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
-    *why = "unsupported tile shape (supported: 28x12, 60x4, 12x28, 28x4, 12x12)";
+  if (p->tile_i > 0 && p->precision == JZ_FP64 && !stage_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
+    *why = "unsupported FP64 tile shape (supported: 28x12, 60x4, 12x28, 28x4, 12x12)";
+    return false;
+  }
+  if (p->tile_i > 0 && p->precision == JZ_FP32_FLUX && !stage32_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
+    *why = "unsupported FP32-flux tile shape (supported: 28x12, 28x20, 12x12)";
     return false;
   }
   if (p->kchunk < 0) {
@@ -169,10 +192,14 @@ struct jz_solver {
   bool owns_ws;
   int device;
   bool grid_set, state_set, dt_valid;
+  int prec;
   double* q0;
-  double* qa;
-  double* qb;
-  double* met;
+  double* qa;       // stage half A (FP64 stage buffer, transposes)
+  double* qb;       // stage half B
+  float* q32a;      // FP32-flux stage states
+  float* q32b;
+  void* met;        // double x 10 (FP64) or float x 9 (FP32-flux) per node
+  double* jac;      // FP32-flux: J per node
   double* norm_part;
   double* lam_part;
   Clock* clock;
@@ -224,7 +251,7 @@ size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
   if (!params_ok(p, &why)) return 0;
   Tiling t;
   pick_tiling(ni, nj, nk, p, &t);
-  return layout_for((long long)ni * nj * nk, t).total;
+  return layout_for((long long)ni * nj * nk, t, p->precision).total;
 }
 
 int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
@@ -244,7 +271,8 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->p = *p;
   s->ph = make_phys(*p);
   pick_tiling(ni, nj, nk, p, &s->tl);
-  s->L = layout_for(s->N, s->tl);
+  s->prec = p->precision;
+  s->L = layout_for(s->N, s->tl, s->prec);
   s->stream = (hipStream_t)hip_stream;
   s->timing = false;
   s->stage_ms_acc = 0;
@@ -277,9 +305,12 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
     s->owns_ws = true;
   }
   s->q0 = (double*)(s->ws + s->L.q0);
-  s->qa = (double*)(s->ws + s->L.qa);
-  s->qb = (double*)(s->ws + s->L.qb);
-  s->met = (double*)(s->ws + s->L.met);
+  s->qa = (double*)(s->ws + s->L.stage);
+  s->qb = s->qa + 5 * s->L.np;
+  s->q32a = s->prec == JZ_FP32_FLUX ? (float*)(s->ws + s->L.q32a) : nullptr;
+  s->q32b = s->prec == JZ_FP32_FLUX ? (float*)(s->ws + s->L.q32b) : nullptr;  // both inside the scratch region
+  s->met = (void*)(s->ws + s->L.met);
+  s->jac = s->prec == JZ_FP32_FLUX ? (double*)(s->ws + s->L.jac) : nullptr;
   s->norm_part = (double*)(s->ws + s->L.norm_part);
   s->lam_part = (double*)(s->ws + s->L.lam_part);
   s->clock = (Clock*)(s->ws + s->L.clock);
@@ -312,16 +343,21 @@ static int clear_flag(jz_solver* s) {
   return JZ_OK;
 }
 
+// Validate the installed metric set (J > 0 and every value finite).
 static int validate_metrics(jz_solver* s, const char* who) {
   int rc = clear_flag(s);
   if (rc) return rc;
-  HIP_TRY(launch_check_metrics(s->met, s->N, s->flag, s->stream));
+  if (s->prec == JZ_FP64)
+    HIP_TRY(launch_check_metrics((const double*)s->met, s->N, s->flag, s->stream));
+  else
+    HIP_TRY(launch_check_met32((const float*)s->met, s->jac, s->N, s->flag, s->stream));
   int f = 0;
   rc = read_flag(s, &f);
   if (rc) return rc;
   if (f) {
     s->grid_set = false;
     clear_flag(s);
+    HIP_TRY(hipStreamSynchronize(s->stream));
     return fail(JZ_EINVAL, "%s: metric set has %s", who, (f & 1) ? "non-finite values" : "non-positive J");
   }
   s->grid_set = true;
@@ -332,27 +368,36 @@ static int validate_metrics(jz_solver* s, const char* who) {
 int jz_set_grid_coords(jz_solver* s, const double* x, const double* y, const double* z, const double* period) {
   if (!s || !x || !y || !z || !period) return fail(JZ_EINVAL, "jz_set_grid_coords: NULL argument");
   const size_t bytes = s->N * sizeof(double);
-  // the coordinates are staged in the (free between steps) stage buffer qa
-  HIP_TRY(hipMemcpyAsync(s->qa, x, bytes, hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(hipMemcpyAsync(s->qa + s->N, y, bytes, hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(hipMemcpyAsync(s->qa + 2 * s->N, z, bytes, hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(launch_metrics_tl(s->qa, period, s->ni, s->nj, s->nk, s->met, s->stream));
+  // coordinates are staged in the scratch region; the metric kernel writes
+  // the stored layout directly (FP64 metrics, or float metrics + double J)
+  double* X = s->qa;
+  HIP_TRY(hipMemcpyAsync(X, x, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(X + s->N, y, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(X + 2 * s->N, z, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(launch_metrics_tl(X, period, s->ni, s->nj, s->nk, s->met, s->jac, s->prec == JZ_FP32_FLUX, s->stream));
   return validate_metrics(s, "jz_set_grid_coords");
 }
 
 int jz_set_grid_metrics(jz_solver* s, const double* m, int on_device) {
   if (!s || !m) return fail(JZ_EINVAL, "jz_set_grid_metrics: NULL argument");
-  // stage the 10 x N array in Qa|Qb, then transpose to the node-major layout
+  // stage the 10 x N array, then convert it to the stored layout
   HIP_TRY(hipMemcpyAsync(s->qa, m, 10 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(launch_soa_to_nodes(s->qa, s->met, s->N, 10, s->stream));
+  if (s->prec == JZ_FP64)
+    HIP_TRY(launch_soa_to_nodes(s->qa, (double*)s->met, s->N, 10, s->stream));
+  else
+    HIP_TRY(launch_soa_to_met32(s->qa, (float*)s->met, s->jac, s->N, s->stream));
   return validate_metrics(s, "jz_set_grid_metrics");
 }
 
 int jz_get_grid_metrics(jz_solver* s, double* m, int on_device) {
   if (!s || !m) return fail(JZ_EINVAL, "jz_get_grid_metrics: NULL argument");
   if (!s->grid_set) return fail(JZ_ESTATE, "jz_get_grid_metrics: no grid set");
-  HIP_TRY(launch_nodes_to_soa(s->met, s->qa, s->N, 10, s->stream));
+  if (s->prec == JZ_FP64) {
+    HIP_TRY(launch_nodes_to_soa((const double*)s->met, s->qa, s->N, 10, s->stream));
+  } else {
+    HIP_TRY(launch_met32_to_soa((const float*)s->met, s->jac, s->qa, s->N, s->stream));
+  }
   HIP_TRY(hipMemcpyAsync(m, s->qa, 10 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -384,12 +429,13 @@ int jz_set_state(jz_solver* s, const double* q, int on_device) {
   return JZ_OK;
 }
 
-static StageArgs stage_args(jz_solver* s, const double* qin, double* qout, double alpha) {
+static StageArgs stage_args(jz_solver* s, const void* qin, void* qout, double alpha) {
   StageArgs a;
   a.qin = qin;
   a.q0 = s->q0;
   a.qout = qout;
   a.met = s->met;
+  a.jac = s->jac;
   a.clock = s->clock;
   a.norm_part = s->norm_part;
   a.lam_part = s->lam_part;
@@ -416,7 +462,8 @@ static StepCtl step_ctl(jz_solver* s) {
 
 static int ensure_dt(jz_solver* s) {
   if (s->dt_valid) return JZ_OK;
-  HIP_TRY(launch_lambda_max(s->q0, s->met, s->N, s->p.gamma, s->lam_part, s->stream));
+  HIP_TRY(launch_lambda_max(s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, s->N, s->p.gamma, s->lam_part,
+                            s->stream));
   HIP_TRY(launch_finalize_dt(s->clock, s->lam_part, lambda_max_blocks(s->N), step_ctl(s), s->flag, s->stream));
   s->dt_valid = true;
   return JZ_OK;
@@ -425,8 +472,36 @@ static int ensure_dt(jz_solver* s) {
 // algorithmic HBM bytes of one stage launch: every array read or written once
 static double stage_bytes(jz_solver* s, int stage) {
   const double n = (double)s->N;
-  if (stage == 0) return n * (40.0 + 80.0 + 40.0);  // Q^n (which is also Q0), metrics, Q(1)
-  return n * (40.0 + 40.0 + 80.0 + 40.0);           // Q(k-1), Q0, metrics, Q(k)
+  const int ns = s->p.n_stages;
+  if (s->prec == JZ_FP64) {
+    if (stage == 0) return n * (40.0 + 80.0 + 40.0);  // Q^n (which is also Q0), metrics, Q(1)
+    return n * (40.0 + 40.0 + 80.0 + 40.0);           // Q(k-1), Q0, metrics, Q(k)
+  }
+  const double met = 36.0 + 8.0;                      // 9 float metrics + double J
+  const double in = stage == 0 ? 40.0 : 20.0;         // double Q^n, else float Q(k-1)
+  const double q0 = stage == 0 ? 0.0 : 40.0;          // Q0 (stage 0 reads it as its stencil)
+  const double out = stage == ns - 1 ? 40.0 : 20.0;   // double Q^{n+1}, else float Q(k)
+  return n * (in + q0 + met + out);
+}
+
+// one stage launch in the solver's precision form; kind as in launch_stage_fp32
+static hipError_t launch_stage(jz_solver* s, const StageArgs& a, int k, int ns, bool residual_only) {
+  if (s->prec == JZ_FP64) {
+    int mode = residual_only ? 4 : ((k == 0 ? 1 : 0) | (k == ns - 1 ? 2 : 0));
+    return launch_stage_fp64(a, s->flag, mode, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream);
+  }
+  int kind;
+  if (residual_only)
+    kind = 4;
+  else if (ns == 1)
+    kind = 3;
+  else if (k == 0)
+    kind = 0;
+  else if (k == ns - 1)
+    kind = 2;
+  else
+    kind = 1;
+  return launch_stage_fp32(a, s->flag, kind, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream);
 }
 
 int jz_advance(jz_solver* s, int nsteps) {
@@ -437,15 +512,15 @@ int jz_advance(jz_solver* s, int nsteps) {
   if (rc) return rc;
   const int ns = s->p.n_stages;
   for (int step = 0; step < nsteps; ++step) {
-    // buffer rotation: Q0 -> Qa -> Qb -> Qa -> Qb -> Q0 (last stage in place:
-    // Q(0) is read only at the node being written)
-    const double* in = s->q0;
+    // buffer rotation: Q0 -> A -> B -> A -> B -> Q0 (last stage in place:
+    // Q(0) is read only at the node being written).  A and B are double
+    // (FP64) or float (FP32-flux) stage states.
+    const void* in = s->q0;
+    void* bufA = s->prec == JZ_FP64 ? (void*)s->qa : (void*)s->q32a;
+    void* bufB = s->prec == JZ_FP64 ? (void*)s->qb : (void*)s->q32b;
     for (int k = 0; k < ns; ++k) {
       const bool last = (k == ns - 1);
-      double* out = last ? s->q0 : ((k % 2 == 0) ? s->qa : s->qb);
-      int mode = 0;
-      if (k == 0) mode |= 1;
-      if (last) mode |= 2;
+      void* out = last ? (void*)s->q0 : ((k % 2 == 0) ? bufA : bufB);
       StageArgs a = stage_args(s, in, out, s->p.rk_alpha[k]);
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (s->timing) {
@@ -453,7 +528,7 @@ int jz_advance(jz_solver* s, int nsteps) {
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, s->stream));
       }
-      HIP_TRY(launch_stage_fp64(a, s->flag, mode, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream));
+      HIP_TRY(launch_stage(s, a, k, ns, false));
       if (s->timing) {
         HIP_TRY(hipEventRecord(e1, s->stream));
         s->ev.emplace_back(e0, e1);
@@ -527,7 +602,7 @@ int jz_eval_residual(jz_solver* s, double* r, int on_device) {
   if (!s || !r) return fail(JZ_EINVAL, "jz_eval_residual: NULL argument");
   if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_eval_residual: grid and state must be set first");
   StageArgs a = stage_args(s, s->q0, s->qa, 0.0);
-  HIP_TRY(launch_stage_fp64(a, s->flag, 4, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream));
+  HIP_TRY(launch_stage(s, a, 0, s->p.n_stages, true));
   HIP_TRY(launch_nodes_to_soa(s->qa, s->qb, s->N, 5, s->stream));
   HIP_TRY(hipMemcpyAsync(r, s->qb, 5 * s->N * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));

@@ -46,7 +46,12 @@ struct CoordView {
 // with X_a2 measured from the centre node; J = 1 / det(delta_d X_a).  Because
 // the centred differences commute, sum_d delta_d S^d_a vanishes identically,
 // which keeps a uniform flow exactly steady on any grid.
-__global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, double* __restrict__ m) {
+// MET32 = false: 10 doubles per node; true: 9 floats per node + J in double.
+template <bool MET32>
+__global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, void* __restrict__ mout,
+                                                         double* __restrict__ jac) {
+  double* m = (double*)mout;
+  float* m32 = (float*)mout;
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= cv.N) return;
   const int i = (int)(n % cv.n[0]);
@@ -71,7 +76,10 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, double* _
       q[d1] -= 1;
       const double t2 = 0.5 * ((cv.at(a2, p[0], p[1], p[2]) - xc) * cv.dd(a1, d2, p[0], p[1], p[2]) -
                                (cv.at(a2, q[0], q[1], q[2]) - xc) * cv.dd(a1, d2, q[0], q[1], q[2]));
-      m[10 * n + 3 * d + a] = t1 - t2;
+      if (MET32)
+        m32[9 * n + 3 * d + a] = (float)(t1 - t2);
+      else
+        m[10 * n + 3 * d + a] = t1 - t2;
     }
   }
   double M[3][3];
@@ -80,7 +88,10 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, double* _
   const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
                      M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
                      M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-  m[10 * n + 9] = 1.0 / det;
+  if (MET32)
+    jac[n] = 1.0 / det;
+  else
+    m[10 * n + 9] = 1.0 / det;
 }
 
 // flag |= 1 for a non-finite metric, |= 2 for J <= 0
@@ -93,6 +104,28 @@ __global__ __launch_bounds__(256) void check_metrics_kernel(const double* __rest
     if (!(m[10 * n + 9] > 0.0)) bad |= 2;
   }
   if (bad) atomicOr(flag, bad);
+}
+
+// same checks on the FP32-flux metric storage
+__global__ __launch_bounds__(256) void check_met32_kernel(const float* __restrict__ m32, const double* __restrict__ jac,
+                                                          long long N, int* __restrict__ flag) {
+  int bad = 0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    for (int c = 0; c < 9; ++c)
+      if (!isfinite(m32[9 * n + c])) bad |= 1;
+    if (!isfinite(jac[n])) bad |= 1;
+    if (!(jac[n] > 0.0)) bad |= 2;
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+// structure-of-arrays metric set (10 x N doubles) -> FP32-flux storage
+__global__ __launch_bounds__(256) void soa_to_met32_kernel(const double* __restrict__ src, float* __restrict__ m32,
+                                                           double* __restrict__ jac, long long N) {
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    for (int k = 0; k < 9; ++k) m32[9 * n + k] = (float)src[k * N + n];
+    jac[n] = src[9 * N + n];
+  }
 }
 
 // flag |= 1 for a non-finite value, |= 2 for rho <= 0 or p <= 0
@@ -111,15 +144,18 @@ __global__ __launch_bounds__(256) void check_state_kernel(const double* __restri
   if (bad) atomicOr(flag, bad);
 }
 
-// per-block max of sum_d lambda^d (grid-stride; max is order-independent)
-__global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restrict__ q, const double* __restrict__ m,
+// per-block max of sum_d lambda^d (grid-stride; max is order-independent).
+// Uses the same metric view and arithmetic as the fused last stage, so the
+// dt of a restarted run is bitwise the dt of the uninterrupted one.
+template <bool MET32>
+__global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restrict__ q, MetView<MET32> met,
                                                          long long N, double gamma, double* __restrict__ part) {
   __shared__ double red[256];
   double mx = 0.0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
     double qq[5], mm[10];
     for (int c = 0; c < 5; ++c) qq[c] = q[5 * n + c];
-    for (int c = 0; c < 10; ++c) mm[c] = m[10 * n + c];
+    met.load(n, mm, mm[9]);
     mx = max_nan(mx, lambda_sum(qq, mm, gamma));
   }
   red[threadIdx.x] = mx;
@@ -129,6 +165,14 @@ __global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restric
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void met32_to_soa_kernel(const float* __restrict__ m32, const double* __restrict__ jac,
+                                                           double* __restrict__ dst, long long N) {
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    for (int k = 0; k < 9; ++k) dst[k * N + n] = (double)m32[9 * n + k];
+    dst[9 * N + n] = jac[n];
+  }
 }
 
 namespace {
@@ -227,8 +271,8 @@ __global__ __launch_bounds__(256) void nodes_to_soa_kernel(const double* __restr
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, double* m,
-                             hipStream_t st) {
+hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, void* m, double* jac,
+                             bool met32, hipStream_t st) {
   CoordView cv;
   cv.X = X;
   cv.N = (long long)ni * nj * nk;
@@ -237,7 +281,10 @@ hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int
   cv.n[2] = nk;
   for (int c = 0; c < 9; ++c) cv.P.p[c] = period9[c];
   const long long nb = (cv.N + 255) / 256;
-  hipLaunchKernelGGL(metrics_tl_kernel, dim3((unsigned)nb), dim3(256), 0, st, cv, m);
+  if (met32)
+    hipLaunchKernelGGL(metrics_tl_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, cv, m, jac);
+  else
+    hipLaunchKernelGGL(metrics_tl_kernel<false>, dim3((unsigned)nb), dim3(256), 0, st, cv, m, jac);
   return hipGetLastError();
 }
 
@@ -248,6 +295,16 @@ static unsigned grid_stride_blocks(long long N) {
 
 hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(check_metrics_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m, N, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(check_met32_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m32, jac, N, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_soa_to_met32(const double* src, float* m32, double* jac, long long N, hipStream_t st) {
+  hipLaunchKernelGGL(soa_to_met32_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, src, m32, jac, N);
   return hipGetLastError();
 }
 
@@ -268,9 +325,24 @@ hipError_t launch_nodes_to_soa(const double* src, double* dst, long long N, int 
 
 int lambda_max_blocks(long long N) { return (int)grid_stride_blocks(N); }
 
-hipError_t launch_lambda_max(const double* q, const double* m, long long N, double gamma, double* part,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(lambda_max_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, m, N, gamma, part);
+hipError_t launch_lambda_max(const double* q, const void* met, const double* jac, bool met32, long long N,
+                             double gamma, double* part, hipStream_t st) {
+  if (met32) {
+    MetView<true> mv;
+    mv.m = (const float*)met;
+    mv.jac = jac;
+    hipLaunchKernelGGL(lambda_max_kernel<true>, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, mv, N, gamma, part);
+  } else {
+    MetView<false> mv;
+    mv.m = (const double*)met;
+    mv.jac = jac;
+    hipLaunchKernelGGL(lambda_max_kernel<false>, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, mv, N, gamma, part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst, long long N, hipStream_t st) {
+  hipLaunchKernelGGL(met32_to_soa_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m32, jac, dst, N);
   return hipGetLastError();
 }
 

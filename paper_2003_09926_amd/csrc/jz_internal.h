@@ -51,10 +51,11 @@ struct Tiling {
 };
 
 struct StageArgs {
-  const double* qin;    // stencil input Q(k-1), 5 x N
-  const double* q0;     // Q(0), 5 x N (read at the owned node only)
-  double* qout;         // Q(k) (or R in residual mode), 5 x N
-  const double* met;    // 10 x N
+  const void* qin;      // stencil input Q(k-1), node-major (double or float)
+  const double* q0;     // Q(0), node-major doubles (read at the owned node only)
+  void* qout;           // Q(k) (or R in residual mode), node-major (double or float)
+  const void* met;      // scaled metrics: 10 doubles per node (J last), or 9 floats per node
+  const double* jac;    // J per node when the metrics are floats (else unused)
   const Clock* clock;   // dt
   double* norm_part;    // [nblocks][10] first-stage partial sums / maxima
   double* lam_part;     // [nblocks] max sum_d lambda^d of the updated state
@@ -89,6 +90,34 @@ __device__ inline double lambda_sum(const double q[5], const double m[10], doubl
   }
   return s;
 }
+
+// Metric views: load the nine scaled metrics of node n in the compute type
+// and J in double.
+template <bool MET32>
+struct MetView;
+template <>
+struct MetView<false> {  // node-major, 10 doubles per node (J last)
+  const double* m;
+  const double* jac;
+  template <typename Rl>
+  __device__ void load(long long n, Rl s[9], double& J) const {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s[k] = (Rl)m[10 * n + k];
+    J = m[10 * n + 9];
+  }
+};
+template <>
+struct MetView<true> {  // node-major, 9 floats per node; J in its own double array
+  const float* m;
+  const double* jac;
+  template <typename Rl>
+  __device__ void load(long long n, Rl s[9], double& J) const {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s[k] = (Rl)m[9 * n + k];
+    J = jac[n];
+  }
+};
+
 
 // Block index -> logical tile, so that the consecutive logical tiles (which
 // share halo rows) land on the same XCD and its L2.  Workgroups are dispatched

@@ -1,0 +1,519 @@
+// jz_stage_kernel.h -- fused residual + Runge-Kutta stage kernel, templated
+// over the arithmetic type (FP64 path and FP32-flux path).
+//
+// One launch performs one stage Q(k) = Q(0) - alpha_k dt R(Q(k-1)) over the
+// whole block (Sec. 3: explicit multistage scheme; Sec. 4.2: each stage runs
+// the full residual -- inviscid flux, viscosity update, viscous flux and
+// artificial dissipation).  R = J (C - D):
+//   C = sum_d delta_d Fhat^d, Fhat^d = sum_a S^d_a (E_a - V_a)       (Eqs. (vec-les), (con-prop))
+//   E_a inviscid flux; V_a viscous flux from the Stokes stress (Eq. (tau_mod)),
+//   Sutherland (Eq. (sutherland)) plus Smagorinsky viscosity and the heat
+//   flux of Eq. (q_mod); gradients are nodal centred differences mapped with
+//   the metrics, so the viscous part reaches two nodes out;
+//   D = sum_d (d_{i+1/2} - d_{i-1/2}), the scalar anisotropic dissipation
+//   with second/fourth differences on the five-point stencil (Sec. 4.3).
+//
+// Work decomposition (2.5-D march):
+//   * a workgroup covers an in-plane tile of TI x TJ owned columns plus a
+//     two-node halo ring, and marches along zeta over a chunk of planes;
+//   * each thread owns one (i, j) column of the tile and keeps the
+//     zeta-direction neighbours of its column in registers (three planes of
+//     Q, the zeta flux and dissipation terms it needs next);
+//   * threads are assigned by role so that whole wavefronts skip the work
+//     their nodes do not need: owned columns first (they do everything), then
+//     the first halo ring without its corners (they need fluxes for one
+//     direction), then the nodes that only supply primitives and Q (ring-1
+//     corners, ring-2 edges); ring-2 corners are never read and get no thread;
+//   * in-plane neighbours are exchanged through LDS, one plane at a time:
+//     primitives, Q and p of the gradient plane; then the xi/eta fluxes,
+//     dissipation scales and pressure sensors of the same plane;
+//   * per march step s the lead plane s+2 is loaded, the gradient plane s+1
+//     gets its fluxes, and plane s gets its residual and is written.
+// Every global access uses periodically wrapped indices, so the halo is the
+// block's own periodic image (standing in for the neighbour-rank ghost
+// layers of Sec. 4.3).  Inside the library Q is stored node-major (the five
+// conserved variables of a node contiguous, 40 B) and the metric set likewise
+// (10 doubles, 80 B per node): one address per node and array, and a
+// wavefront still reads one contiguous span per plane row.
+//
+// Precision forms (template parameters Rl, TIn, TOut, MET32):
+//   FP64:      everything in double; metrics node-major, 10 doubles per node.
+//   FP32-flux: primitives, gradients, viscosities, fluxes and dissipation in
+//              float, read from a float copy of the stencil input (stages 2-5)
+//              and float metrics (9 per node); J stays double, R = J (C - D)
+//              is formed in double and Q(k) = Q(0) - alpha_k dt R is
+//              accumulated in double from the double Q(0); intermediate stage
+//              states are stored in float (they only feed the next stage's
+//              stencil), the last stage stores double.  Residual norms and the
+//              CFL reduction stay double.
+#pragma once
+#include "jz_internal.h"
+
+namespace jz {
+
+namespace {
+
+template <typename Rl>
+struct Prim {
+  Rl u, v, w, T, p;
+};
+
+// FP64 reciprocal and square root for positive, normal arguments: hardware
+// seed refined by Newton (reciprocal) and Goldschmidt (square root)
+// iterations to full double precision.  Non-positive or non-finite inputs
+// give NaN/Inf, which the norm and dt checks then report.
+__device__ inline double rcp_pos(double y) {
+  double r = __builtin_amdgcn_rcp(y);
+  double e = fma(-y, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-y, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ inline double div_pos(double x, double y) {
+  const double r = rcp_pos(y);
+  const double q = x * r;
+  return fma(fma(-y, q, x), r, q);
+}
+
+__device__ inline double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// FP32 counterparts: hardware approximations (about 1 ulp), which is the
+// accuracy the FP32-flux form works at
+__device__ inline float rcp_pos(float y) { return __builtin_amdgcn_rcpf(y); }
+__device__ inline float div_pos(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+__device__ inline float sqrt_pos(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+template <typename Rl>
+__device__ inline Prim<Rl> primitives(const Rl q[5], Rl gm1, Rl gamma) {
+  Prim<Rl> r;
+  const Rl rinv = rcp_pos(q[0]);
+  r.u = q[1] * rinv;
+  r.v = q[2] * rinv;
+  r.w = q[3] * rinv;
+  r.p = gm1 * (q[4] - Rl(0.5) * q[0] * (r.u * r.u + r.v * r.v + r.w * r.w));
+  r.T = gamma * r.p * rinv;
+  return r;
+}
+
+// J^(-1/3) (the filter width of a cell of volume 1/J): float seed from the
+// hardware log2/exp2, then two Newton steps r <- r + r (1 - J r^3) / 3 in FP64,
+// which square the relative error twice (1e-7 -> 1e-14 -> below rounding).
+__device__ inline double inv_cbrt(double J) {
+  const float jf = (float)J;
+  double r = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(jf) * (1.0f / 3.0f));
+  r = r + r * (1.0 - J * r * r * r) * (1.0 / 3.0);
+  r = r + r * (1.0 - J * r * r * r) * (1.0 / 3.0);
+  return r;
+}
+
+// J^(-1/3) in float: hardware log2/exp2 seed and one Newton step
+__device__ inline float inv_cbrt(float J) {
+  float r = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(J) * (1.0f / 3.0f));
+  return r + r * (1.0f - J * r * r * r) * (1.0f / 3.0f);
+}
+
+template <typename Rl>
+__device__ inline Rl sensor(Rl pm, Rl p0, Rl pp) {
+  return div_pos(fabs(pp - Rl(2) * p0 + pm), pp + Rl(2) * p0 + pm);
+}
+
+
+// Role of thread t in a TI x TJ tile with a two-node halo: position (tx, ty)
+// in the (TI+4) x (TJ+4) tile and role 0 = owned column, 1 = first-ring edge
+// (needs fluxes), 2 = primitives and Q only, 3 = idle.
+template <int TI, int TJ>
+__device__ inline int tile_role(int t, int& tx, int& ty) {
+  constexpr int NI = TI * TJ, NR = 2 * TI + 2 * TJ;
+  if (t < NI) {
+    tx = 2 + t % TI;
+    ty = 2 + t / TI;
+    return 0;
+  }
+  int r = t - NI;
+  int ring = 1, role = 1;
+  if (r >= NR) {
+    r -= NR;
+    role = 2;
+    if (r < 4) {  // first-ring corners
+      tx = (r & 1) ? TI + 2 : 1;
+      ty = (r & 2) ? TJ + 2 : 1;
+      return 2;
+    }
+    r -= 4;
+    if (r >= NR) {
+      tx = ty = 0;
+      return 3;
+    }
+    ring = 2;
+  }
+  const int lo = 2 - ring, hi_i = TI + 1 + ring, hi_j = TJ + 1 + ring;
+  if (r < TI) {
+    tx = 2 + r;
+    ty = lo;
+  } else if (r < 2 * TI) {
+    tx = 2 + r - TI;
+    ty = hi_j;
+  } else if (r < 2 * TI + TJ) {
+    tx = lo;
+    ty = 2 + r - 2 * TI;
+  } else {
+    tx = hi_i;
+    ty = 2 + r - 2 * TI - TJ;
+  }
+  return role;
+}
+
+}  // namespace
+
+// MODE bit 0: accumulate norms of R (first stage)
+// MODE bit 1: max of sum_d lambda^d of the updated state (last stage -> next dt)
+// MODE bit 2: write R itself instead of the stage update
+template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
+__global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
+  constexpr int NT = BX * BY;
+  constexpr int TI = BX - 4, TJ = BY - 4;
+  constexpr bool NORMS = (MODE & 1) != 0;
+  constexpr bool LAMMAX = (MODE & 2) != 0;
+  constexpr bool WRITE_R = (MODE & 4) != 0;
+  static_assert(TI * TJ + 4 * TI + 4 * TJ + 4 <= NT, "tile roles exceed the workgroup");
+
+  // plane buffers (structure of arrays, one slot per thread/column)
+  __shared__ Rl sPr[3][5][NT];     // ring of three planes of u, v, w, T, p
+  __shared__ Rl sQ[5][NT];         // Q of the gradient plane
+  __shared__ Rl sF[10][NT];        // Fhat^xi (rows 0-4) and Fhat^eta (rows 5-9) of the gradient plane
+  Rl(*sFx)[NT] = sF;
+  Rl(*sFy)[NT] = sF + 5;
+  __shared__ Rl sSx[NT], sSy[NT];  // sigma^xi, sigma^eta
+  __shared__ Rl sNx[NT], sNy[NT];  // pressure sensor along xi, eta
+  __shared__ double sRed[2][NT];   // end-of-kernel reductions
+
+  if (*flag) return;  // a failed step froze the state
+
+  const Phys ph = A.ph;
+  const Rl gm1 = (Rl)ph.gm1, gamma = (Rl)ph.gamma;
+  const Rl k2 = (Rl)ph.k2, k4 = (Rl)ph.k4;
+  const int nb = gridDim.x;
+  const int lt = xcd_remap(blockIdx.x, nb);
+  const int tile_i = lt % A.tiles_i;
+  const int rest = lt / A.tiles_i;
+  const int tile_j = rest % A.tiles_j;
+  const int chunk = rest / A.tiles_j;
+  const int i0 = tile_i * TI, j0 = tile_j * TJ;
+  const int kbeg = chunk * A.kchunk;
+  const int kend = min(kbeg + A.kchunk, A.nk);
+
+  const int t = threadIdx.x;
+  int tx, ty;
+  const int role = tile_role<TI, TJ>(t, tx, ty);
+  const int c = tx + BX * ty;                     // LDS slot of this column
+  const int ui = i0 - 2 + tx, uj = j0 - 2 + ty;  // unwrapped column indices
+  const long long col = (long long)wrap_index(ui, A.ni) + (long long)A.ni * wrap_index(uj, A.nj);
+  const long long plane = (long long)A.ni * A.nj;
+  const bool isP = role <= 2;                     // supplies primitives and Q
+  const bool isG = role <= 1;                     // computes fluxes
+  const bool isI = role == 0 && ui < A.ni && uj < A.nj;  // owns (writes) its column
+
+  const TIn* __restrict__ qin = (const TIn*)A.qin;
+  TOut* __restrict__ qout = (TOut*)A.qout;
+  MetView<MET32> met;
+  met.m = (decltype(met.m))A.met;
+  met.jac = A.jac;
+  const double dt = A.clock->dt;
+  const double adt = A.alpha * dt;
+
+  auto node = [&](int k) { return col + plane * wrap_index(k, A.nk); };
+  auto put_prims = [&](int slot, const Rl q[5]) {
+    if (!isP) return;
+    const Prim<Rl> p = primitives(q, gm1, gamma);
+    sPr[slot][0][c] = p.u;
+    sPr[slot][1][c] = p.v;
+    sPr[slot][2][c] = p.w;
+    sPr[slot][3][c] = p.T;
+    sPr[slot][4][c] = p.p;
+  };
+
+  // column registers: Q of planes s-1 (m), s, s+1 (g) and the lead s+2 (l)
+  Rl Qm[5], Qs[5], Qg[5], Ql[5];
+  Rl nus = 0, sigs = 0;
+  double Js = 0.0;
+  Rl Fzs[5] = {0, 0, 0, 0, 0}, Hm[5] = {0, 0, 0, 0, 0}, Rin[5] = {0, 0, 0, 0, 0};
+  double nsum[5] = {0, 0, 0, 0, 0}, nmax[5] = {0, 0, 0, 0, 0};
+  double lmax = 0.0;
+
+  // software prefetch, one march step ahead: Q of the next lead plane and
+  // the metrics of the next gradient plane
+  Rl Qn[5], Mn[9];
+  double MJn = 0.0;
+
+  // ring slots: plane k lives in slot (k - kbeg + 3) % 3
+  int slot_s = 1, slot_g = 2, slot_l = 0;  // planes kbeg-2, kbeg-1, kbeg
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Qs[v] = Qg[v] = Qn[v] = Qm[v] = 0;
+  if (isP) {
+    const long long n0 = node(kbeg - 2), n1 = node(kbeg - 1), n2 = node(kbeg);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Qs[v] = (Rl)qin[5 * n0 + v];
+      Qg[v] = (Rl)qin[5 * n1 + v];
+      Qn[v] = (Rl)qin[5 * n2 + v];
+    }
+    if (isG) met.load(n1, Mn, MJn);
+    put_prims(slot_s, Qs);
+    put_prims(slot_g, Qg);
+  }
+
+  for (int s = kbeg - 2; s < kend; ++s) {
+    // ---- lead plane s+2 (prefetched); prefetch plane s+3 -------------------
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Ql[v] = Qn[v];
+    if (isP && s + 3 < kend + 2) {
+      const long long nn = node(s + 3);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Qn[v] = (Rl)qin[5 * nn + v];
+    }
+    __syncthreads();  // the previous step's readers of slot_l, sQ, sF*, sS*, sN* are done
+    put_prims(slot_l, Ql);
+    if (isP) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sQ[v][c] = Qg[v];
+    }
+    __syncthreads();
+
+    // ---- gradient plane g = s+1: fluxes, dissipation scales, sensors ------
+    Rl Fzg[5] = {0, 0, 0, 0, 0}, sigg = 0, nug = 0;
+    double Jg = 0.0;
+    if (isG) {
+      Rl m[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = Mn[k];
+      Jg = MJn;
+      if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
+      const Rl J = (Rl)Jg;
+      const Rl(*Pg)[NT] = sPr[slot_g];
+      // chain rule d phi / d x_a = J sum_d S^d_a delta_d phi, with the 1/2 of
+      // the centred difference folded into the metric factor
+      Rl hm[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) hm[k] = (Rl(0.5) * J) * m[k];
+      Rl gr[4][3];  // gr[q][a] = d phi_q / d x_a for phi = u, v, w, T
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const Rl dxi = Pg[q][c + 1] - Pg[q][c - 1];
+        const Rl deta = Pg[q][c + BX] - Pg[q][c - BX];
+        const Rl dzeta = sPr[slot_l][q][c] - sPr[slot_s][q][c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gr[q][a] = hm[a] * dxi + hm[3 + a] * deta + hm[6 + a] * dzeta;
+      }
+      const Rl uu[3] = {Pg[0][c], Pg[1][c], Pg[2][c]};
+      const Rl T = Pg[3][c], p = Pg[4][c];
+      const Rl asnd = sqrt_pos(T);
+      const Rl mu = div_pos((Rl)ph.mu_suth * T * asnd, T + (Rl)ph.suth_s);
+      // Smagorinsky: |S| = sqrt(2 S_ab S_ab), Delta = J^(-1/3)
+      const Rl s01 = gr[0][1] + gr[1][0], s02 = gr[0][2] + gr[2][0], s12 = gr[1][2] + gr[2][1];
+      const Rl ss2 = Rl(2) * (gr[0][0] * gr[0][0] + gr[1][1] * gr[1][1] + gr[2][2] * gr[2][2]) +
+                     (s01 * s01 + s02 * s02 + s12 * s12);
+      const Rl smag = ss2 > Rl(0) ? sqrt_pos(ss2) : Rl(0);
+      const Rl delta = inv_cbrt(J);
+      const Rl mut = Qg[0] * (Rl)ph.cs2 * delta * delta * smag;
+      const Rl kap = (Rl)ph.kap_lam * mu + (Rl)ph.kap_turb * mut;
+      const Rl mue = mu + mut;
+      const Rl div23 = (Rl(2) / Rl(3)) * (gr[0][0] + gr[1][1] + gr[2][2]);
+      // Fhat^d = sum_a S^d_a (E_a - V_a), one Cartesian column a at a time
+      Rl F[3][5];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Rl ta[3];  // column a of the stress tensor
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ta[r] = mue * (gr[r][a] + gr[a][r] - (r == a ? div23 : Rl(0)));
+        Rl ev[5];
+        ev[0] = Qg[0] * uu[a];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ev[1 + r] = Qg[1 + r] * uu[a] + (r == a ? p : Rl(0)) - ta[r];
+        ev[4] = (Qg[4] + p) * uu[a] - (uu[0] * ta[0] + uu[1] * ta[1] + uu[2] * ta[2] + kap * gr[3][a]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int v = 0; v < 5; ++v) F[d][v] = (a == 0) ? m[3 * d] * ev[v] : fma(m[3 * d + a], ev[v], F[d][v]);
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        sFx[v][c] = F[0][v];
+        sFy[v][c] = F[1][v];
+        Fzg[v] = F[2][v];
+      }
+      // spectral radii and anisotropic dissipation scales
+      Rl lam[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const Rl sx = m[3 * d], sy = m[3 * d + 1], sz = m[3 * d + 2];
+        lam[d] = fabs(J * (sx * uu[0] + sy * uu[1] + sz * uu[2])) + asnd * J * sqrt_pos(sx * sx + sy * sy + sz * sz);
+      }
+      Rl sig[3];
+      const Rl jinv = rcp_pos(J);
+      if (ph.alpha_half) {
+        // phi^d lambda^d = lambda^d + sum_{e != d} sqrt(lambda^e lambda^d)
+        const Rl r0 = sqrt_pos(lam[0]), r1 = sqrt_pos(lam[1]), r2 = sqrt_pos(lam[2]);
+        const Rl rs = (r0 + r1 + r2) * jinv;
+        sig[0] = r0 * rs;
+        sig[1] = r1 * rs;
+        sig[2] = r2 * rs;
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          Rl phi = 1;
+#pragma unroll
+          for (int e = 0; e < 3; ++e)
+            if (e != d) phi += (Rl)pow((double)lam[e] / (double)lam[d], ph.tv_alpha);
+          sig[d] = phi * lam[d] * jinv;
+        }
+      }
+      sSx[c] = sig[0];
+      sSy[c] = sig[1];
+      sigg = sig[2];
+      sNx[c] = sensor(Pg[4][c - 1], p, Pg[4][c + 1]);
+      sNy[c] = sensor(Pg[4][c - BX], p, Pg[4][c + BX]);
+      nug = sensor(sPr[slot_s][4][c], p, sPr[slot_l][4][c]);
+    }
+    __syncthreads();
+
+    // ---- owned columns: in-plane terms of plane g, zeta face, residual of s ----
+    if (isI) {
+      Rl Rg[5];
+      {
+        // xi faces t-1/2 and t+1/2, eta faces t-BX/2 and t+BX/2
+        const Rl e2xp = k2 * fmax(sNx[c], sNx[c + 1]);
+        const Rl e2xm = k2 * fmax(sNx[c - 1], sNx[c]);
+        const Rl e4xp = fmax(Rl(0), k4 - e2xp), e4xm = fmax(Rl(0), k4 - e2xm);
+        const Rl sgxp = Rl(0.5) * (sSx[c] + sSx[c + 1]), sgxm = Rl(0.5) * (sSx[c - 1] + sSx[c]);
+        const Rl e2yp = k2 * fmax(sNy[c], sNy[c + BX]);
+        const Rl e2ym = k2 * fmax(sNy[c - BX], sNy[c]);
+        const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
+        const Rl sgyp = Rl(0.5) * (sSy[c] + sSy[c + BX]), sgym = Rl(0.5) * (sSy[c - BX] + sSy[c]);
+#pragma unroll 1
+        for (int v = 0; v < 5; ++v) {
+          const Rl q0 = sQ[v][c];
+          const Rl qxp = sQ[v][c + 1], qxpp = sQ[v][c + 2], qxm = sQ[v][c - 1], qxmm = sQ[v][c - 2];
+          const Rl qyp = sQ[v][c + BX], qypp = sQ[v][c + 2 * BX], qym = sQ[v][c - BX], qymm = sQ[v][c - 2 * BX];
+          const Rl dxp = sgxp * (e2xp * (qxp - q0) - e4xp * ((qxpp - qxm) - Rl(3) * (qxp - q0)));
+          const Rl dxm = sgxm * (e2xm * (q0 - qxm) - e4xm * ((qxp - qxmm) - Rl(3) * (q0 - qxm)));
+          const Rl dyp = sgyp * (e2yp * (qyp - q0) - e4yp * ((qypp - qym) - Rl(3) * (qyp - q0)));
+          const Rl dym = sgym * (e2ym * (q0 - qym) - e4ym * ((qyp - qymm) - Rl(3) * (q0 - qym)));
+          const Rl cx = Rl(0.5) * (sFx[v][c + 1] - sFx[v][c - 1]);
+          const Rl cy = Rl(0.5) * (sFy[v][c + BX] - sFy[v][c - BX]);
+          Rg[v] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
+        }
+      }
+      if (s >= kbeg - 1) {
+        // zeta face between planes s and s+1
+        const Rl e2 = k2 * fmax(nus, nug);
+        const Rl e4 = fmax(Rl(0), k4 - e2);
+        const Rl sg = Rl(0.5) * (sigs + sigg);
+        Rl Hp[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const Rl d3 = (Ql[v] - Qm[v]) - Rl(3) * (Qg[v] - Qs[v]);
+          Hp[v] = Rl(0.5) * (Fzs[v] + Fzg[v]) - sg * (e2 * (Qg[v] - Qs[v]) - e4 * d3);
+        }
+        if (s >= kbeg) {
+          const long long ns = node(s);
+          double R[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) R[v] = Js * (double)(Rin[v] + (Hp[v] - Hm[v]));
+          if (WRITE_R) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)R[v];
+          } else {
+            double qn[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+              qn[v] = A.q0[5 * ns + v] - adt * R[v];
+              qout[5 * ns + v] = (TOut)qn[v];
+            }
+            if (LAMMAX) {
+              double m[10];
+              met.load(ns, m, m[9]);
+              lmax = max_nan(lmax, lambda_sum(qn, m, ph.gamma));
+            }
+          }
+          if (NORMS) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+              nsum[v] += R[v] * R[v];
+              nmax[v] = max_nan(nmax[v], fabs(R[v]));
+            }
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Hm[v] = Hp[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Rin[v] = Rg[v];
+    }
+
+    // ---- shift the column registers and the ring by one plane ---------------
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Qm[v] = Qs[v];
+      Qs[v] = Qg[v];
+      Qg[v] = Ql[v];
+      Fzs[v] = Fzg[v];
+    }
+    nus = nug;
+    sigs = sigg;
+    Js = Jg;
+    const int old_s = slot_s;
+    slot_s = slot_g;
+    slot_g = slot_l;
+    slot_l = old_s;
+  }
+
+  // ---- deterministic block reductions (fixed tree order) --------------------
+  if (NORMS || LAMMAX) {
+    // one quantity at a time through the two double rows of sRed
+    for (int q = 0; q < (NORMS ? 5 : 0) + (LAMMAX ? 1 : 0); ++q) {
+      __syncthreads();
+      const bool isnorm = NORMS && q < 5;
+      sRed[0][t] = isnorm ? nsum[q] : 0.0;
+      sRed[1][t] = isnorm ? nmax[q] : lmax;
+      __syncthreads();
+      // fold to a power of two, then a fixed binary tree
+      constexpr int P2 = (NT & (NT - 1)) == 0 ? NT : (1 << (31 - __builtin_clz(NT)));
+      if (P2 != NT) {
+        if (t < NT - P2) {
+          sRed[0][t] += sRed[0][t + P2];
+          sRed[1][t] = max_nan(sRed[1][t], sRed[1][t + P2]);
+        }
+        __syncthreads();
+      }
+      for (int st = P2 / 2; st > 0; st >>= 1) {
+        if (t < st) {
+          sRed[0][t] += sRed[0][t + st];
+          sRed[1][t] = max_nan(sRed[1][t], sRed[1][t + st]);
+        }
+        __syncthreads();
+      }
+      if (t == 0) {
+        if (isnorm) {
+          A.norm_part[(long long)blockIdx.x * 10 + q] = sRed[0][0];
+          A.norm_part[(long long)blockIdx.x * 10 + 5 + q] = sRed[1][0];
+        } else {
+          A.lam_part[blockIdx.x] = sRed[1][0];
+        }
+      }
+    }
+  }
+}
+
+
+}  // namespace jz
