@@ -153,8 +153,46 @@ int jz_eval_dt(jz_solver* s, double* dt, double* lambda_max);
 int jz_set_timing(jz_solver* s, int enable);
 int jz_get_timing(jz_solver* s, double* stage_ms, long long* stage_launches, double* stage_bytes);
 
+/* Change the launch shape (tile_i x tile_j owned columns per workgroup, kchunk
+ * planes marched per workgroup; 0 = default) of an existing solver.  Results
+ * do not depend on it (each node's arithmetic is the same for every shape).
+ * JZ_EINVAL for an unsupported shape. */
+int jz_set_tiling(jz_solver* s, int tile_i, int tile_j, int kchunk);
+int jz_get_tiling(jz_solver* s, int* tile_i, int* tile_j, int* kchunk);
+
 /* Release the solver (and the workspace if the library allocated it). */
 int jz_destroy(jz_solver* s);
+
+/* ---- batches: many uneven blocks advanced together ----------------------
+ * A batch advances several solvers (its members, which keep their own
+ * grids, states, clocks, dt and flags) with one persistent launch per RK
+ * stage over the tiles of all members, and one finalize launch; the step is
+ * captured once in a hipGraph and replayed.  Members must share precision,
+ * stage count and coefficients, and a tile shape with a batch kernel
+ * (FP64: 28x12, 12x12; FP32-flux: 28x20, 28x12, 12x12), and must have their
+ * grid and state set.  Each member's results are bitwise those of the member
+ * advanced alone with the same tile shape.  The caller keeps ownership of the
+ * members and must not advance them on their own while the batch is in use.
+ * hip_stream orders the batch against the caller's work (NULL = null
+ * stream); the batch runs on an internal non-blocking stream. */
+typedef struct jz_batch jz_batch;
+int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, jz_batch** out);
+int jz_batch_advance(jz_batch* b, int nsteps);
+/* Rebuild the member table after jz_set_tiling on members. */
+int jz_batch_refresh(jz_batch* b);
+/* 1 (default): replay a captured hipGraph per step; 0: launch directly. */
+int jz_batch_set_graph(jz_batch* b, int enable);
+/* Pick the fastest launch shape by timing trial_steps steps per candidate;
+ * member states and clocks are restored afterwards.  cache_path (may be NULL)
+ * names a text file of earlier choices keyed by the batch's shapes. */
+int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int* tile_i, int* tile_j,
+                      int* kchunk, double* best_step_ms);
+/* Step timing with hipEvents: summed milliseconds and number of steps since
+ * timing was enabled, and the total node count of the members. */
+int jz_batch_set_timing(jz_batch* b, int enable);
+int jz_batch_get_timing(jz_batch* b, double* step_ms, long long* steps, long long* points);
+int jz_batch_synchronize(jz_batch* b);
+int jz_batch_destroy(jz_batch* b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* jz_last_error(void);

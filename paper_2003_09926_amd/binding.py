@@ -74,6 +74,18 @@ def library() -> ctypes.CDLL:
         "jz_set_timing": ([S, i], i),
         "jz_get_timing": ([S, ctypes.POINTER(d), ctypes.POINTER(ll), ctypes.POINTER(d)], i),
         "jz_destroy": ([S], i),
+        "jz_set_tiling": ([S, i, i, i], i),
+        "jz_get_tiling": ([S, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "jz_batch_create": ([ctypes.POINTER(S), i, ctypes.c_void_p, ctypes.POINTER(S)], i),
+        "jz_batch_advance": ([S, i], i),
+        "jz_batch_refresh": ([S], i),
+        "jz_batch_set_graph": ([S, i], i),
+        "jz_batch_autotune": ([S, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i),
+                               ctypes.POINTER(i), ctypes.POINTER(d)], i),
+        "jz_batch_set_timing": ([S, i], i),
+        "jz_batch_get_timing": ([S, ctypes.POINTER(d), ctypes.POINTER(ll), ctypes.POINTER(ll)], i),
+        "jz_batch_synchronize": ([S], i),
+        "jz_batch_destroy": ([S], i),
         "jz_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -226,11 +238,81 @@ class Solver:
                "jz_get_timing")
         return ms.value, n.value, b.value
 
+    def set_tiling(self, tile_i: int, tile_j: int, kchunk: int = 0):
+        _check(library().jz_set_tiling(self._h, tile_i, tile_j, kchunk), "jz_set_tiling")
+
+    def tiling(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(library().jz_get_tiling(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "jz_get_tiling")
+        return a.value, b.value, c.value
+
     def close(self):
         if getattr(self, "_h", None):
             library().jz_destroy(self._h)
             self._h = None
         self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Advance several Solvers together (one persistent launch per stage,
+    step replayed from a hipGraph).  The members stay owned by the caller."""
+
+    def __init__(self, members, stream=None):
+        import torch
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(library().jz_batch_create(arr, len(self.members), ctypes.c_void_p(self._stream.cuda_stream),
+                                         ctypes.byref(h)), "jz_batch_create")
+        self._h = h
+
+    def advance(self, nsteps: int):
+        _check(library().jz_batch_advance(self._h, int(nsteps)), "jz_batch_advance")
+
+    def refresh(self):
+        _check(library().jz_batch_refresh(self._h), "jz_batch_refresh")
+
+    def set_graph(self, enable: bool):
+        _check(library().jz_batch_set_graph(self._h, 1 if enable else 0), "jz_batch_set_graph")
+
+    def autotune(self, trial_steps: int = 3, cache_path: Optional[str] = None):
+        a, b, c, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(library().jz_batch_autotune(self._h, int(trial_steps),
+                                           cache_path.encode() if cache_path else None,
+                                           ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                           ctypes.byref(ms)), "jz_batch_autotune")
+        return (a.value, b.value, c.value), ms.value
+
+    def set_timing(self, enable: bool):
+        _check(library().jz_batch_set_timing(self._h, 1 if enable else 0), "jz_batch_set_timing")
+
+    def timing(self):
+        ms, n, pts = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
+        _check(library().jz_batch_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pts)),
+               "jz_batch_get_timing")
+        return ms.value, n.value, pts.value
+
+    def synchronize(self):
+        _check(library().jz_batch_synchronize(self._h), "jz_batch_synchronize")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().jz_batch_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,13 @@ hipError_t launch_stage_fp32(const StageArgs& a, const int* flag, int kind, int 
                              hipStream_t st);
 bool stage_shape_supported(int bx, int by);
 bool stage32_shape_supported(int bx, int by);
+bool batch64_shape_supported(int bx, int by);
+bool batch32_shape_supported(int bx, int by);
+hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
+                                   int bx, int by, int grid_cap, int total, hipStream_t st);
+hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
+                                   int bx, int by, int grid_cap, int total, hipStream_t st);
+hipError_t launch_finalize_batch(const BlockDesc* desc, int nblk, hipStream_t st);
 hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst, long long N, hipStream_t st);
 hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, void* m, double* jac,
                              bool met32, hipStream_t st);
@@ -92,7 +100,15 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
 }
 
-Layout layout_for(long long N, const Tiling& t, int prec) {
+// Tiles of the finest supported tiling (interior 12 x 4 tiles with 8-plane
+// chunks bounds every shape in either precision), so the partial-sum arrays
+// never need to grow when the tiling changes.
+int partial_capacity(int ni, int nj, int nk, const Tiling& t) {
+  const int fine = ((ni + 11) / 12) * ((nj + 3) / 4) * ((nk + 7) / 8);
+  return fine > t.nblocks ? fine : t.nblocks;
+}
+
+Layout layout_for(long long N, const Tiling& t, int prec, int cap) {
   Layout L;
   std::memset(&L, 0, sizeof L);
   size_t off = 0;
@@ -112,8 +128,8 @@ Layout layout_for(long long N, const Tiling& t, int prec) {
     L.met = take(9 * N * sizeof(float));
     L.jac = take(N * sizeof(double));
   }
-  L.norm_part = take((size_t)t.nblocks * 10 * sizeof(double));
-  const int lb = t.nblocks > lambda_max_blocks(N) ? t.nblocks : lambda_max_blocks(N);
+  L.norm_part = take((size_t)cap * 10 * sizeof(double));
+  const int lb = cap > lambda_max_blocks(N) ? cap : lambda_max_blocks(N);
   L.lam_part = take((size_t)lb * sizeof(double));
   L.clock = take(sizeof(Clock));
   L.flag = take(4 * sizeof(int));
@@ -186,6 +202,7 @@ struct jz_solver {
   jz_params p;
   Phys ph;
   Tiling tl;
+  int cap;          // tiles the partial-sum arrays can hold
   Layout L;
   hipStream_t stream;
   char* ws;
@@ -251,7 +268,7 @@ size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
   if (!params_ok(p, &why)) return 0;
   Tiling t;
   pick_tiling(ni, nj, nk, p, &t);
-  return layout_for((long long)ni * nj * nk, t, p->precision).total;
+  return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t)).total;
 }
 
 int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
@@ -272,7 +289,8 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->ph = make_phys(*p);
   pick_tiling(ni, nj, nk, p, &s->tl);
   s->prec = p->precision;
-  s->L = layout_for(s->N, s->tl, s->prec);
+  s->cap = partial_capacity(ni, nj, nk, s->tl);
+  s->L = layout_for(s->N, s->tl, s->prec, s->cap);
   s->stream = (hipStream_t)hip_stream;
   s->timing = false;
   s->stage_ms_acc = 0;
@@ -659,6 +677,31 @@ int jz_get_timing(jz_solver* s, double* stage_ms, long long* stage_launches, dou
   return JZ_OK;
 }
 
+int jz_set_tiling(jz_solver* s, int tile_i, int tile_j, int kchunk) {
+  if (!s) return fail(JZ_EINVAL, "jz_set_tiling: NULL solver");
+  jz_params p = s->p;
+  p.tile_i = tile_i;
+  p.tile_j = tile_j;
+  p.kchunk = kchunk;
+  std::string why;
+  if (!params_ok(&p, &why)) return fail(JZ_EINVAL, "jz_set_tiling: %s", why.c_str());
+  Tiling t;
+  pick_tiling(s->ni, s->nj, s->nk, &p, &t);
+  if (t.nblocks > s->cap) return fail(JZ_EINVAL, "jz_set_tiling: %d tiles exceed the %d the workspace holds", t.nblocks, s->cap);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->p = p;
+  s->tl = t;
+  return JZ_OK;
+}
+
+int jz_get_tiling(jz_solver* s, int* tile_i, int* tile_j, int* kchunk) {
+  if (!s) return fail(JZ_EINVAL, "jz_get_tiling: NULL solver");
+  if (tile_i) *tile_i = s->tl.ti;
+  if (tile_j) *tile_j = s->tl.tj;
+  if (kchunk) *kchunk = s->tl.kchunk;
+  return JZ_OK;
+}
+
 int jz_destroy(jz_solver* s) {
   if (!s) return JZ_OK;
   (void)hipStreamSynchronize(s->stream);
@@ -672,5 +715,412 @@ int jz_destroy(jz_solver* s) {
 }
 
 const char* jz_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ===========================================================================
+// batches of blocks
+// ===========================================================================
+struct jz_batch {
+  std::vector<jz_solver*> m;
+  int prec, ns, bx, by;
+  double alpha[5];
+  hipStream_t user;
+  hipStream_t st;          // internal non-blocking stream (graph capture needs one)
+  hipEvent_t ev_in, ev_out;
+  BlockDesc* d_desc;
+  int* d_off;
+  int total;               // tiles of all members
+  long long npoints;
+  bool use_graph, graph_ok;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double ms_acc;
+  long long steps_acc;
+};
+
+namespace {
+
+void batch_drop_graph(jz_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_ok = false;
+}
+
+int batch_upload(jz_batch* b) {
+  const int n = (int)b->m.size();
+  std::vector<BlockDesc> d(n);
+  std::vector<int> off(n + 1, 0);
+  b->npoints = 0;
+  for (int i = 0; i < n; ++i) {
+    jz_solver* s = b->m[i];
+    BlockDesc& D = d[i];
+    D.q0 = s->q0;
+    D.bufA = s->prec == JZ_FP64 ? (void*)s->qa : (void*)s->q32a;
+    D.bufB = s->prec == JZ_FP64 ? (void*)s->qb : (void*)s->q32b;
+    D.met = s->met;
+    D.jac = s->jac;
+    D.clock = s->clock;
+    D.norm_part = s->norm_part;
+    D.lam_part = s->lam_part;
+    D.flag = s->flag;
+    D.N = s->N;
+    D.ni = s->ni;
+    D.nj = s->nj;
+    D.nk = s->nk;
+    D.tiles_i = s->tl.tiles_i;
+    D.tiles_j = s->tl.tiles_j;
+    D.kchunk = s->tl.kchunk;
+    D.nchunks = s->tl.nchunks;
+    D.ntiles = s->tl.nblocks;
+    D.ctl = step_ctl(s);
+    D.ph = s->ph;
+    off[i + 1] = off[i] + s->tl.nblocks;
+    b->npoints += s->N;
+  }
+  b->total = off[n];
+  HIP_TRY(hipMemcpyAsync(b->d_desc, d.data(), n * sizeof(BlockDesc), hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipMemcpyAsync(b->d_off, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipStreamSynchronize(b->st));
+  batch_drop_graph(b);
+  return JZ_OK;
+}
+
+// one full step of every member on b->st
+int batch_step_launches(jz_batch* b) {
+  const int n = (int)b->m.size();
+  for (int k = 0; k < b->ns; ++k) {
+    if (b->prec == JZ_FP64)
+      HIP_TRY(launch_stage_batch_fp64(b->d_desc, b->d_off, n, k, b->ns, b->alpha[k], b->bx, b->by, 0, b->total,
+                                      b->st));
+    else
+      HIP_TRY(launch_stage_batch_fp32(b->d_desc, b->d_off, n, k, b->ns, b->alpha[k], b->bx, b->by, 0, b->total,
+                                      b->st));
+  }
+  HIP_TRY(launch_finalize_batch(b->d_desc, n, b->st));
+  return JZ_OK;
+}
+
+int batch_ensure_dt(jz_batch* b) {
+  for (jz_solver* s : b->m) {
+    if (s->dt_valid) continue;
+    hipStream_t keep = s->stream;
+    s->stream = b->st;
+    int rc = ensure_dt(s);
+    s->stream = keep;
+    if (rc) return rc;
+  }
+  return JZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, jz_batch** out) {
+  if (!out) return fail(JZ_EINVAL, "jz_batch_create: out is NULL");
+  *out = nullptr;
+  if (!members || nmembers < 1) return fail(JZ_EINVAL, "jz_batch_create: no members");
+  jz_solver* f = members[0];
+  if (!f) return fail(JZ_EINVAL, "jz_batch_create: NULL member");
+  for (int i = 0; i < nmembers; ++i) {
+    jz_solver* s = members[i];
+    if (!s) return fail(JZ_EINVAL, "jz_batch_create: NULL member %d", i);
+    if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_batch_create: member %d has no grid or state", i);
+    if (s->prec != f->prec || s->p.n_stages != f->p.n_stages || s->tl.bx != f->tl.bx || s->tl.by != f->tl.by)
+      return fail(JZ_EINVAL, "jz_batch_create: member %d differs in precision, stage count or tile shape", i);
+    for (int k = 0; k < f->p.n_stages; ++k)
+      if (s->p.rk_alpha[k] != f->p.rk_alpha[k])
+        return fail(JZ_EINVAL, "jz_batch_create: member %d has other stage coefficients", i);
+    for (int j = 0; j < i; ++j)
+      if (members[j] == s) return fail(JZ_EINVAL, "jz_batch_create: member %d repeated", i);
+  }
+  const bool shape_ok = f->prec == JZ_FP64 ? batch64_shape_supported(f->tl.bx, f->tl.by)
+                                            : batch32_shape_supported(f->tl.bx, f->tl.by);
+  if (!shape_ok) return fail(JZ_EINVAL, "jz_batch_create: tile shape %dx%d has no batch kernel", f->tl.ti, f->tl.tj);
+  jz_batch* b = new jz_batch();
+  b->m.assign(members, members + nmembers);
+  b->prec = f->prec;
+  b->ns = f->p.n_stages;
+  b->bx = f->tl.bx;
+  b->by = f->tl.by;
+  for (int k = 0; k < 5; ++k) b->alpha[k] = f->p.rk_alpha[k];
+  b->user = (hipStream_t)hip_stream;
+  b->d_desc = nullptr;
+  b->d_off = nullptr;
+  b->use_graph = true;
+  b->graph_ok = false;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->timing = false;
+  b->ms_acc = 0;
+  b->steps_acc = 0;
+  hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_desc, nmembers * sizeof(BlockDesc));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_off, (nmembers + 1) * sizeof(int));
+  for (jz_solver* s : b->m)
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    jz_batch_destroy(b);
+    return fail(JZ_EHIP, "jz_batch_create: %s", hipGetErrorString(e));
+  }
+  int rc = batch_upload(b);
+  if (rc) {
+    jz_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return JZ_OK;
+}
+
+int jz_batch_set_graph(jz_batch* b, int enable) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_set_graph: NULL batch");
+  b->use_graph = enable != 0;
+  return JZ_OK;
+}
+
+int jz_batch_refresh(jz_batch* b) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_refresh: NULL batch");
+  for (jz_solver* s : b->m)
+    if (s->tl.bx != b->bx || s->tl.by != b->by) {
+      const bool ok = b->prec == JZ_FP64 ? batch64_shape_supported(s->tl.bx, s->tl.by)
+                                         : batch32_shape_supported(s->tl.bx, s->tl.by);
+      if (!ok) return fail(JZ_EINVAL, "jz_batch_refresh: tile shape has no batch kernel");
+    }
+  b->bx = b->m[0]->tl.bx;
+  b->by = b->m[0]->tl.by;
+  for (jz_solver* s : b->m)
+    if (s->tl.bx != b->bx || s->tl.by != b->by) return fail(JZ_EINVAL, "jz_batch_refresh: members differ in tile shape");
+  return batch_upload(b);
+}
+
+int jz_batch_advance(jz_batch* b, int nsteps) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_advance: NULL batch");
+  if (nsteps < 0) return fail(JZ_EINVAL, "jz_batch_advance: nsteps < 0");
+  HIP_TRY(hipEventRecord(b->ev_in, b->user));
+  HIP_TRY(hipStreamWaitEvent(b->st, b->ev_in, 0));
+  int rc = batch_ensure_dt(b);
+  if (rc) return rc;
+  if (b->use_graph && !b->graph_ok && nsteps > 0) {
+    HIP_TRY(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    rc = batch_step_launches(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->st, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(JZ_EHIP, "jz_batch_advance: capture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_ok = true;
+  }
+  for (int step = 0; step < nsteps; ++step) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->timing) {
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      HIP_TRY(hipEventRecord(e0, b->st));
+    }
+    if (b->use_graph) {
+      HIP_TRY(hipGraphLaunch(b->exec, b->st));
+    } else {
+      rc = batch_step_launches(b);
+      if (rc) return rc;
+    }
+    if (b->timing) {
+      HIP_TRY(hipEventRecord(e1, b->st));
+      b->ev.emplace_back(e0, e1);
+    }
+  }
+  for (jz_solver* s : b->m) s->dt_valid = true;
+  HIP_TRY(hipEventRecord(b->ev_out, b->st));
+  HIP_TRY(hipStreamWaitEvent(b->user, b->ev_out, 0));
+  for (jz_solver* s : b->m)
+    if (s->stream != b->user) HIP_TRY(hipStreamWaitEvent(s->stream, b->ev_out, 0));
+  return JZ_OK;
+}
+
+int jz_batch_set_timing(jz_batch* b, int enable) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_set_timing: NULL batch");
+  HIP_TRY(hipStreamSynchronize(b->st));
+  for (auto& pr : b->ev) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  b->ev.clear();
+  b->ms_acc = 0;
+  b->steps_acc = 0;
+  b->timing = enable != 0;
+  return JZ_OK;
+}
+
+int jz_batch_get_timing(jz_batch* b, double* step_ms, long long* steps, long long* points) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_get_timing: NULL batch");
+  HIP_TRY(hipStreamSynchronize(b->st));
+  for (auto& pr : b->ev) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    b->ms_acc += ms;
+    b->steps_acc += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  b->ev.clear();
+  if (step_ms) *step_ms = b->ms_acc;
+  if (steps) *steps = b->steps_acc;
+  if (points) *points = b->npoints;
+  return JZ_OK;
+}
+
+int jz_batch_synchronize(jz_batch* b) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_synchronize: NULL batch");
+  HIP_TRY(hipStreamSynchronize(b->st));
+  return JZ_OK;
+}
+
+// Try each candidate launch shape (tile shape with a batch kernel in this
+// precision x planes per chunk) for trial_steps steps after one warm-up step,
+// keep the fastest, and put every member back to the state and clock it had
+// before.  The member states are saved in temporary device buffers.  A cache
+// file (one "key tile_i tile_j kchunk ms" line per batch signature) skips the
+// trials for a batch seen before.
+int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int* tile_i, int* tile_j, int* kchunk,
+                      double* best_ms) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_autotune: NULL batch");
+  if (trial_steps < 1) return fail(JZ_EINVAL, "jz_batch_autotune: trial_steps < 1");
+  // batch signature: precision, stage count and the sorted member shapes
+  std::vector<long long> shapes;
+  for (jz_solver* s : b->m) shapes.push_back(((long long)s->ni << 40) | ((long long)s->nj << 20) | s->nk);
+  std::sort(shapes.begin(), shapes.end());
+  unsigned long long h = 1469598103934665603ull;
+  for (long long v : shapes) h = (h ^ (unsigned long long)v) * 1099511628211ull;
+  char key[64];
+  snprintf(key, sizeof key, "p%d-s%d-n%zu-%016llx", b->prec, b->ns, b->m.size(), h);
+  int best_ti = -1, best_tj = -1, best_kc = -1;
+  double best = 1e300;
+  if (cache_path) {
+    FILE* fp = fopen(cache_path, "r");
+    if (fp) {
+      char k[64];
+      int a1, a2, a3;
+      double ms;
+      while (fscanf(fp, "%63s %d %d %d %lf", k, &a1, &a2, &a3, &ms) == 5)
+        if (strcmp(k, key) == 0) {
+          best_ti = a1;
+          best_tj = a2;
+          best_kc = a3;
+          best = ms;
+        }
+      fclose(fp);
+    }
+  }
+  if (best_ti < 0) {
+    std::vector<std::pair<int, int>> cand;
+    if (b->prec == JZ_FP64)
+      cand = {{28, 12}, {12, 12}};
+    else
+      cand = {{28, 20}, {28, 12}, {12, 12}};
+    const int kcs[3] = {16, 32, 64};
+    // save states and clocks
+    std::vector<double*> qsave(b->m.size(), nullptr);
+    std::vector<Clock> csave(b->m.size());
+    HIP_TRY(hipStreamSynchronize(b->st));
+    int rc = JZ_OK;
+    for (size_t i = 0; i < b->m.size() && rc == JZ_OK; ++i) {
+      jz_solver* s = b->m[i];
+      if (hipMalloc((void**)&qsave[i], 5 * s->N * sizeof(double)) != hipSuccess) rc = fail(JZ_ENOMEM, "autotune save");
+      if (rc == JZ_OK && hipMemcpy(qsave[i], s->q0, 5 * s->N * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess)
+        rc = fail(JZ_EHIP, "autotune save copy");
+      if (rc == JZ_OK && hipMemcpy(&csave[i], s->clock, sizeof(Clock), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(JZ_EHIP, "autotune clock copy");
+    }
+    auto restore = [&]() -> int {
+      for (size_t i = 0; i < b->m.size(); ++i) {
+        jz_solver* s = b->m[i];
+        if (!qsave[i]) continue;
+        HIP_TRY(hipMemcpy(s->q0, qsave[i], 5 * s->N * sizeof(double), hipMemcpyDeviceToDevice));
+        HIP_TRY(hipMemcpy(s->clock, &csave[i], sizeof(Clock), hipMemcpyHostToDevice));
+        const int z = 0;
+        HIP_TRY(hipMemcpy(s->flag, &z, sizeof z, hipMemcpyHostToDevice));
+        s->dt_valid = false;
+      }
+      return JZ_OK;
+    };
+    const bool timing_was = b->timing;
+    for (size_t c = 0; c < cand.size() && rc == JZ_OK; ++c)
+      for (int kk = 0; kk < 3 && rc == JZ_OK; ++kk) {
+        bool ok = true;
+        for (jz_solver* s : b->m)
+          if (jz_set_tiling(s, cand[c].first, cand[c].second, kcs[kk]) != JZ_OK) ok = false;
+        if (!ok) continue;
+        rc = batch_upload(b);
+        b->bx = cand[c].first + 4;
+        b->by = cand[c].second + 4;
+        if (rc == JZ_OK) rc = jz_batch_set_timing(b, 0);
+        if (rc == JZ_OK) rc = jz_batch_advance(b, 1);
+        if (rc == JZ_OK) rc = jz_batch_set_timing(b, 1);
+        if (rc == JZ_OK) rc = jz_batch_advance(b, trial_steps);
+        double ms = 0;
+        long long n = 0;
+        if (rc == JZ_OK) rc = jz_batch_get_timing(b, &ms, &n, nullptr);
+        if (rc == JZ_OK && n > 0 && ms / n < best) {
+          best = ms / n;
+          best_ti = cand[c].first;
+          best_tj = cand[c].second;
+          best_kc = kcs[kk];
+        }
+        if (rc == JZ_OK) rc = restore();
+      }
+    jz_batch_set_timing(b, timing_was ? 1 : 0);
+    for (double* p : qsave)
+      if (p) (void)hipFree(p);
+    if (rc) return rc;
+    if (best_ti < 0) return fail(JZ_EINVAL, "jz_batch_autotune: no candidate shape fits the members");
+    if (cache_path) {
+      FILE* fp = fopen(cache_path, "a");
+      if (fp) {
+        fprintf(fp, "%s %d %d %d %.6f\n", key, best_ti, best_tj, best_kc, best);
+        fclose(fp);
+      }
+    }
+  }
+  for (jz_solver* s : b->m) {
+    int rc = jz_set_tiling(s, best_ti, best_tj, best_kc);
+    if (rc) return rc;
+  }
+  b->bx = best_ti + 4;
+  b->by = best_tj + 4;
+  int rc = batch_upload(b);
+  if (rc) return rc;
+  if (tile_i) *tile_i = best_ti;
+  if (tile_j) *tile_j = best_tj;
+  if (kchunk) *kchunk = best_kc;
+  if (best_ms) *best_ms = best;
+  return JZ_OK;
+}
+
+int jz_batch_destroy(jz_batch* b) {
+  if (!b) return JZ_OK;
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  for (auto& pr : b->ev) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  batch_drop_graph(b);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_off) (void)hipFree(b->d_off);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  delete b;
+  return JZ_OK;
+}
 
 }  // extern "C"

@@ -224,12 +224,12 @@ __global__ __launch_bounds__(FIN_T) void finalize_dt_kernel(Clock* clk, const do
   }
 }
 
+namespace {
 // end of a step: advance the clock by the dt just used, store the first-stage
 // norms, and set the next dt from the last stage's lambda partials
-__global__ __launch_bounds__(FIN_T) void finalize_step_kernel(Clock* clk, const double* __restrict__ norm_part,
-                                                              const double* __restrict__ lam_part, int nb,
-                                                              StepCtl ctl, int* __restrict__ flag) {
-  __shared__ double red[FIN_T];
+__device__ void finalize_step_body(Clock* clk, const double* __restrict__ norm_part,
+                                   const double* __restrict__ lam_part, int nb, const StepCtl& ctl,
+                                   int* __restrict__ flag, double* red) {
   if (*flag) return;
   double sums[5], maxs[5];
   for (int v = 0; v < 5; ++v) {
@@ -252,6 +252,21 @@ __global__ __launch_bounds__(FIN_T) void finalize_step_kernel(Clock* clk, const 
     ok = ok && isfinite(lmax) && isfinite(dt) && dt > 0.0;
     if (!ok) *flag |= 1;
   }
+}
+}  // namespace
+
+__global__ __launch_bounds__(FIN_T) void finalize_step_kernel(Clock* clk, const double* __restrict__ norm_part,
+                                                              const double* __restrict__ lam_part, int nb,
+                                                              StepCtl ctl, int* __restrict__ flag) {
+  __shared__ double red[FIN_T];
+  finalize_step_body(clk, norm_part, lam_part, nb, ctl, flag, red);
+}
+
+// one workgroup per member block of a batch
+__global__ __launch_bounds__(FIN_T) void finalize_batch_kernel(const BlockDesc* __restrict__ desc) {
+  __shared__ double red[FIN_T];
+  const BlockDesc& D = desc[blockIdx.x];
+  finalize_step_body(D.clock, D.norm_part, D.lam_part, D.ntiles, D.ctl, D.flag, red);
 }
 
 // structure-of-arrays (c x N, the ABI layout) <-> node-major (N x c, the
@@ -348,6 +363,11 @@ hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst,
 
 hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCtl ctl, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(FIN_T), 0, st, clk, lam_part, nb, ctl, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const BlockDesc* desc, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(nblk), dim3(FIN_T), 0, st, desc);
   return hipGetLastError();
 }
 

@@ -66,6 +66,26 @@ struct StageArgs {
   Phys ph;
 };
 
+// One member block of a batch: its device buffers, shape and physics.  The
+// stage buffers rotate Q0 -> A -> B -> A -> ... -> Q0 as in the single-block
+// path.
+struct BlockDesc {
+  double* q0;
+  void* bufA;
+  void* bufB;
+  const void* met;
+  const double* jac;
+  Clock* clock;
+  double* norm_part;
+  double* lam_part;
+  int* flag;
+  long long N;
+  int ni, nj, nk;
+  int tiles_i, tiles_j, kchunk, nchunks, ntiles;
+  StepCtl ctl;
+  Phys ph;
+};
+
 __host__ __device__ inline int wrap_index(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

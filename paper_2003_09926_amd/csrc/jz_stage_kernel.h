@@ -179,8 +179,11 @@ __device__ inline int tile_role(int t, int& tx, int& ty) {
 // MODE bit 0: accumulate norms of R (first stage)
 // MODE bit 1: max of sum_d lambda^d of the updated state (last stage -> next dt)
 // MODE bit 2: write R itself instead of the stage update
+// One tile (logical index lt of the block described by A) through one stage.
+// Partial norms and lambda maxima go to slot lt, so the reductions do not
+// depend on how tiles are scheduled.  Every thread of the workgroup calls it.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
+__device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr int NT = BX * BY;
   constexpr int TI = BX - 4, TJ = BY - 4;
   constexpr bool NORMS = (MODE & 1) != 0;
@@ -198,13 +201,9 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* _
   __shared__ Rl sNx[NT], sNy[NT];  // pressure sensor along xi, eta
   __shared__ double sRed[2][NT];   // end-of-kernel reductions
 
-  if (*flag) return;  // a failed step froze the state
-
   const Phys ph = A.ph;
   const Rl gm1 = (Rl)ph.gm1, gamma = (Rl)ph.gamma;
   const Rl k2 = (Rl)ph.k2, k4 = (Rl)ph.k4;
-  const int nb = gridDim.x;
-  const int lt = xcd_remap(blockIdx.x, nb);
   const int tile_i = lt % A.tiles_i;
   const int rest = lt / A.tiles_i;
   const int tile_j = rest % A.tiles_j;
@@ -505,15 +504,72 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* _
       }
       if (t == 0) {
         if (isnorm) {
-          A.norm_part[(long long)blockIdx.x * 10 + q] = sRed[0][0];
-          A.norm_part[(long long)blockIdx.x * 10 + 5 + q] = sRed[1][0];
+          A.norm_part[(long long)lt * 10 + q] = sRed[0][0];
+          A.norm_part[(long long)lt * 10 + 5 + q] = sRed[1][0];
         } else {
-          A.lam_part[blockIdx.x] = sRed[1][0];
+          A.lam_part[lt] = sRed[1][0];
         }
       }
     }
   }
 }
 
+
+// Single block: one workgroup per tile, tiles spread XCD by XCD.
+template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
+__global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
+  if (*flag) return;  // a failed step froze the state
+  stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Many blocks in one persistent launch.  The tiles of all blocks form one
+// global list (block b owns [tile_off[b], tile_off[b+1])).  XCD x takes a
+// contiguous share of the list, so neighbouring tiles of a block meet in one
+// L2; the workgroups resident on that XCD walk their share with a fixed
+// stride, and every workgroup exits once its share is done.
+template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
+__global__ __launch_bounds__(BX* BY) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
+                                                             const int* __restrict__ tile_off, int nblk,
+                                                             int stage, int nstages, double alpha) {
+  constexpr int NX = 8;
+  const int total = tile_off[nblk];
+  const int x = blockIdx.x % NX;
+  const int per_x = (gridDim.x - x + NX - 1) / NX;  // workgroups on this XCD
+  const int w = blockIdx.x / NX;
+  const int lo = (int)((long long)total * x / NX), hi = (int)((long long)total * (x + 1) / NX);
+  for (int g = lo + w; g < hi; g += per_x) {
+    // block owning global tile g (uniform over the workgroup)
+    int a = 0, b = nblk;
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (tile_off[mid] <= g) a = mid;
+      else b = mid;
+    }
+    const BlockDesc& D = desc[a];
+    if (*D.flag) continue;
+    StageArgs A;
+    const bool last = stage == nstages - 1;
+    A.qin = stage == 0 ? (const void*)D.q0 : ((stage - 1) % 2 == 0 ? D.bufA : D.bufB);
+    A.qout = last ? (void*)D.q0 : (stage % 2 == 0 ? D.bufA : D.bufB);
+    A.q0 = D.q0;
+    A.met = D.met;
+    A.jac = D.jac;
+    A.clock = D.clock;
+    A.norm_part = D.norm_part;
+    A.lam_part = D.lam_part;
+    A.alpha = alpha;
+    A.N = D.N;
+    A.ni = D.ni;
+    A.nj = D.nj;
+    A.nk = D.nk;
+    A.tiles_i = D.tiles_i;
+    A.tiles_j = D.tiles_j;
+    A.kchunk = D.kchunk;
+    A.nchunks = D.nchunks;
+    A.ph = D.ph;
+    __syncthreads();  // the previous tile's LDS readers are done
+    stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, g - tile_off[a]);
+  }
+}
 
 }  // namespace jz

@@ -1,0 +1,142 @@
+"""Batched form: many uneven blocks advanced by one persistent launch per
+stage, the step replayed from a hipGraph.  Every member must come out bitwise
+identical to the same block advanced alone (same tile shape), in both
+precision forms; a member that fails is frozen without disturbing the rest."""
+import numpy as np
+import pytest
+
+from paper_2003_09926_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(37, 23, 19), (20, 33, 12), (48, 16, 30), (9, 11, 13), (64, 40, 24), (31, 31, 31)]
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2003_09926_amd import binding
+    binding.library()
+    return binding
+
+
+def _cases():
+    out = []
+    for b, d in enumerate(DIMS):
+        g = I.uniform_box(*d)
+        q = I.jet_state(g, 1.2 + 0.1 * b, seed=100 + b)
+        out.append((g, q, dict(mach_j=1.2 + 0.1 * b, re_d=10 ** (5 + 0.2 * b))))
+    return out
+
+
+def _members(B, cases, prec, tile, **extra):
+    ms = []
+    for g, q, kw in cases:
+        s = B.Solver(g.dims, B.params_default(precision=prec, tile_i=tile[0], tile_j=tile[1], **kw, **extra))
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        ms.append(s)
+    return ms
+
+
+@pytest.mark.parametrize("prec,tile", [(0, (28, 12)), (0, (12, 12)), (1, (28, 20)), (1, (12, 12))])
+def test_batch_members_bitwise_equal_alone(B, prec, tile):
+    print(f"[gpu-case] batch vs alone precision={prec} tile={tile}", flush=True)
+    cases = _cases()
+    alone = []
+    for s in _members(B, cases, prec, tile):
+        s.advance(3)
+        alone.append((s.get_state(), s.residual_norms(), s.clock()))
+        s.close()
+    ms = _members(B, cases, prec, tile)
+    with B.Batch(ms) as b:
+        b.advance(3)
+        b.synchronize()
+    for s, (q, (rms, linf), clk) in zip(ms, alone):
+        assert np.array_equal(s.get_state(), q)
+        r2, l2 = s.residual_norms()
+        assert np.array_equal(r2, rms) and np.array_equal(l2, linf)
+        assert s.clock() == clk
+        s.close()
+
+
+def test_graph_and_direct_launches_agree(B):
+    print("[gpu-case] batch graph vs direct", flush=True)
+    cases = _cases()
+    res = []
+    for graph in (True, False):
+        ms = _members(B, cases, 0, (28, 12))
+        with B.Batch(ms) as b:
+            b.set_graph(graph)
+            b.advance(2)
+            b.advance(1)
+            b.synchronize()
+        res.append([s.get_state() for s in ms])
+        for s in ms:
+            s.close()
+    for a, c in zip(*res):
+        assert np.array_equal(a, c)
+
+
+def test_autotune_keeps_results(B, tmp_path):
+    print("[gpu-case] batch autotune", flush=True)
+    cases = _cases()[:4]
+    ref = []
+    for s in _members(B, cases, 0, (28, 12)):
+        s.advance(2)
+        ref.append(s.get_state())
+        s.close()
+    ms = _members(B, cases, 0, (28, 12))
+    cache = str(tmp_path / "tune.txt")
+    with B.Batch(ms) as b:
+        choice, best_ms = b.autotune(trial_steps=1, cache_path=cache)
+        assert choice[0] in (28, 12) and best_ms > 0
+        b.advance(2)
+        b.synchronize()
+        choice2, _ = b.autotune(trial_steps=1, cache_path=cache)   # from the cache
+        assert choice2 == choice
+    for s, q in zip(ms, ref):
+        assert np.array_equal(s.get_state(), q)
+        s.close()
+    assert open(cache).read().count("\n") == 1
+
+
+def test_failing_member_is_isolated(B):
+    """One member with a fixed dt far beyond stability blows up; it is
+    flagged and frozen, the others match their solo runs bitwise."""
+    print("[gpu-case] batch failing member", flush=True)
+    cases = _cases()[:3]
+    solo = []
+    for s in _members(B, cases, 0, (28, 12)):
+        s.advance(4)
+        solo.append(s.get_state())
+        s.close()
+    ms = _members(B, cases[:2], 0, (28, 12))
+    g, q, kw = cases[2]
+    bad = B.Solver(g.dims, B.params_default(tile_i=28, tile_j=12, dt_fixed=5.0, **kw))
+    bad.set_grid_metrics(g.metrics)
+    bad.set_state(q)
+    with B.Batch(ms + [bad]) as b:
+        b.advance(4)
+        b.synchronize()
+    for s, qs in zip(ms, solo[:2]):
+        assert np.array_equal(s.get_state(), qs)
+    with pytest.raises(B.JzError) as ei:
+        bad.get_state()
+    assert ei.value.code == B.JZ_ENONFINITE
+    for s in ms + [bad]:
+        s.close()
+
+
+def test_batch_rejects_mixed_members(B):
+    cases = _cases()[:2]
+    a = _members(B, cases[:1], 0, (28, 12))[0]
+    c = _members(B, cases[1:], 1, (28, 12))[0]
+    with pytest.raises(B.JzError) as ei:
+        B.Batch([a, c])
+    assert ei.value.code == B.JZ_EINVAL
+    with pytest.raises(B.JzError):
+        B.Batch([a, a])
+    a.close()
+    c.close()
