@@ -216,15 +216,53 @@ def run_batch(prec_name: str, steps: int, warmup: int):
     }
 
 
+def run_serve(prec_name: str, nruns: int, with_sequential: bool):
+    """Config 5: Poisson arrivals (mean 20 runs/s, seed 5) of cubic jet runs
+    n^3, n uniform in [48, 192], Mach U[1.2, 2.0], Re_D log-uniform
+    [1e5, 1e6], 200 steps each at CFL 0.5, admitted under a 200 GB budget,
+    served by continuous batching; compared with each run alone, one at a
+    time in arrival order."""
+    import torch
+    from paper_2003_09926_amd import binding as B
+    from paper_2003_09926_amd import inputs as I
+    from paper_2003_09926_amd import serve as S
+
+    torch.cuda.set_device(0)
+    prec = B.JZ_FP64 if prec_name == "fp64" else B.JZ_FP32_FLUX
+    tile = (28, 12)
+    stream = I.arrival_stream(seed=5, nruns=nruns, rate=20.0)
+    runs = S.make_runs(stream)
+    srv = S.JetServer(precision=prec, budget_bytes=200 << 30, max_resident=32, chunk_steps=20, tile=tile)
+    st = srv.serve(runs)
+    summ = st.summary()
+    out = {
+        "metric": "point-stage updates/s", "value": summ["point_stage_updates_per_s"],
+        "unit": "point-stage updates/s", "n_gpus": 1, "steps": 200, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == B.JZ_FP64 else "f32 (fluxes) + f64 (accumulation, J, norms)",
+        "data": "synthetic",
+        "config": {"workload": f"served_jet_runs_{prec_name}", "runs": nruns, "arrival_rate_per_s": 20.0,
+                   "n_range": [48, 192], "steps_per_run": 200, "budget_gb": 200, "max_resident": 32,
+                   "chunk_steps": 20, "seed": 5, "form": f"serve-{prec_name}"},
+        "serve": summ,
+    }
+    if with_sequential:
+        out["alone_sequential"] = S.sequential_baseline(runs, prec, tile)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="fp64", choices=["fp64", "fp32", "batch-fp64", "batch-fp32"],
+    ap.add_argument("--form", default="fp64",
+                    choices=["fp64", "fp32", "batch-fp64", "batch-fp32", "serve-fp64", "serve-fp32"],
                     help="fp64: FP64 path (default); fp32: FP32-flux form on the same workload; "
                          "batch-*: 64 uneven blocks in one persistent launch per stage")
     ap.add_argument("--no-error", action="store_true", help="fp32 form: skip the error-vs-oracle run")
+    ap.add_argument("--runs", type=int, default=100, help="serve forms: length of the arrival stream")
+    ap.add_argument("--no-sequential", action="store_true", help="serve forms: skip the alone baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB "
@@ -247,6 +285,8 @@ def main(argv=None):
     rank = int(os.environ.get("RANK", "0"))
     if a.form.startswith("batch"):
         out = run_batch(a.form.split("-")[1], a.steps, a.warmup)
+    elif a.form.startswith("serve"):
+        out = run_serve(a.form.split("-")[1], a.runs, not a.no_sequential)
     else:
         out = run_block(a.form, a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu),
                         with_error=not a.no_error)

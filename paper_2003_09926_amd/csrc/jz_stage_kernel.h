@@ -523,18 +523,21 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* _
 }
 
 // Many blocks in one persistent launch.  The tiles of all blocks form one
-// global list (block b owns [tile_off[b], tile_off[b+1])).  XCD x takes a
+// global list (block b owns [tile_off[b], tile_off[b+1])).  Slot x (the XCD
+// that workgroups with blockIdx % 8 == x are dispatched to) takes a
 // contiguous share of the list, so neighbouring tiles of a block meet in one
-// L2; the workgroups resident on that XCD walk their share with a fixed
-// stride, and every workgroup exits once its share is done.
+// L2; the workgroups of a slot walk its share with a fixed stride, and every
+// workgroup exits once its share is done.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
                                                              const int* __restrict__ tile_off, int nblk,
                                                              int stage, int nstages, double alpha) {
-  constexpr int NX = 8;
+  // at most 8 slots, and never more slots than workgroups, so that every
+  // slot (and with it every tile) has at least one workgroup
+  const int NX = gridDim.x < 8 ? (int)gridDim.x : 8;
   const int total = tile_off[nblk];
   const int x = blockIdx.x % NX;
-  const int per_x = (gridDim.x - x + NX - 1) / NX;  // workgroups on this XCD
+  const int per_x = (gridDim.x - x + NX - 1) / NX;  // workgroups in this slot
   const int w = blockIdx.x / NX;
   const int lo = (int)((long long)total * x / NX), hi = (int)((long long)total * (x + 1) / NX);
   for (int g = lo + w; g < hi; g += per_x) {

@@ -140,3 +140,27 @@ def test_batch_rejects_mixed_members(B):
         B.Batch([a, a])
     a.close()
     c.close()
+
+
+def test_tiny_batch_with_fewer_tiles_than_xcds(B):
+    """A batch of two small blocks has fewer tiles than there are XCD slots;
+    every tile must still be processed exactly once."""
+    print("[gpu-case] tiny batch", flush=True)
+    cases = [(I.uniform_box(5, 5, 5), 1.3, 51), (I.uniform_box(9, 11, 13), 1.7, 52)]
+    solo, members = [], []
+    for g, mach, seed in cases:
+        q = I.jet_state(g, mach, seed)
+        for store in (solo, members):
+            s = B.Solver(g.dims, B.params_default(tile_i=28, tile_j=12, mach_j=mach))
+            s.set_grid_metrics(g.metrics)
+            s.set_state(q)
+            store.append(s)
+    for s in solo:
+        s.advance(3)
+    with B.Batch(members) as b:
+        b.advance(3)
+        b.synchronize()
+    for a, c in zip(solo, members):
+        assert np.array_equal(a.get_state(), c.get_state())
+        a.close()
+        c.close()
