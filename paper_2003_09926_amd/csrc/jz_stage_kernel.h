@@ -47,6 +47,8 @@
 //              stencil), the last stage stores double.  Residual norms and the
 //              CFL reduction stay double.
 #pragma once
+
+#include <type_traits>
 #include "jz_internal.h"
 
 namespace jz {
@@ -193,13 +195,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 
   // plane buffers (structure of arrays, one slot per thread/column)
   __shared__ Rl sPr[3][5][NT];     // ring of three planes of u, v, w, T, p
-  __shared__ Rl sQ[5][NT];         // Q of the gradient plane
-  __shared__ Rl sF[10][NT];        // Fhat^xi (rows 0-4) and Fhat^eta (rows 5-9) of the gradient plane
+  __shared__ Rl sQ2[2][5][NT];     // Q of the gradient plane, alternating between two buffers
+  __shared__ __attribute__((aligned(16))) Rl sF[10][NT];  // Fhat^xi (rows 0-4), Fhat^eta (rows 5-9)
   Rl(*sFx)[NT] = sF;
   Rl(*sFy)[NT] = sF + 5;
   __shared__ Rl sSx[NT], sSy[NT];  // sigma^xi, sigma^eta
   __shared__ Rl sNx[NT], sNy[NT];  // pressure sensor along xi, eta
-  __shared__ double sRed[2][NT];   // end-of-kernel reductions
+  // end-of-tile reductions reuse the flux buffer (free once the march is done)
+  double(*sRed)[NT] = reinterpret_cast<double(*)[NT]>(&sF[0][0]);
 
   const Phys ph = A.ph;
   const Rl gm1 = (Rl)ph.gm1, gamma = (Rl)ph.gamma;
@@ -230,6 +233,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   met.jac = A.jac;
   const double dt = A.clock->dt;
   const double adt = A.alpha * dt;
+  const bool q0_is_input = (const void*)A.qin == (const void*)A.q0;
 
   auto node = [&](int k) { return col + plane * wrap_index(k, A.nk); };
   auto put_prims = [&](int slot, const Rl q[5]) {
@@ -281,7 +285,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Qn[v] = (Rl)qin[5 * nn + v];
     }
-    __syncthreads();  // the previous step's readers of slot_l, sQ, sF*, sS*, sN* are done
+    // No barrier here: slot_l was last read in the previous step's gradient
+    // phase (before its second barrier), and Q goes to the other half of sQ2.
+    // The flux, scale and sensor buffers are rewritten only after the next
+    // barrier, which every thread reaches after finishing the owned phase.
+    Rl(*sQ)[NT] = sQ2[(s - kbeg) & 1];
     put_prims(slot_l, Ql);
     if (isP) {
 #pragma unroll
@@ -434,11 +442,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
             for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)R[v];
           } else {
             double qn[5];
+            // In the first stage the stencil input is Q(0) itself and, in the
+            // FP64 form, the column registers hold it exactly: no re-read.
+            if (std::is_same<Rl, double>::value && std::is_same<TIn, double>::value && q0_is_input) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-              qn[v] = A.q0[5 * ns + v] - adt * R[v];
-              qout[5 * ns + v] = (TOut)qn[v];
+              for (int v = 0; v < 5; ++v) qn[v] = (double)Qs[v] - adt * R[v];
+            } else {
+#pragma unroll
+              for (int v = 0; v < 5; ++v) qn[v] = A.q0[5 * ns + v] - adt * R[v];
             }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)qn[v];
             if (LAMMAX) {
               double m[10];
               met.load(ns, m, m[9]);
