@@ -71,7 +71,8 @@ typedef struct {
   int n_stages;        /* 1..5 (5) */
   int precision;       /* jz_precision (JZ_FP64) */
   int tile_i, tile_j;  /* launch shape of the stage kernel; 0 = library default */
-  int kchunk;          /* planes marched per workgroup; 0 = library default */
+  int kchunk;          /* planes marched per workgroup; 0 = chosen by the library for
+                          the current device (fills the last round of workgroups) */
 } jz_params;
 
 /* Fill *p with the defaults listed above. */

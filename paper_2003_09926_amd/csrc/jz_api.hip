@@ -19,6 +19,8 @@ hipError_t launch_stage_fp32(const StageArgs& a, const int* flag, int kind, int 
 bool stage_shape_supported(int bx, int by);
 bool stage32_shape_supported(int bx, int by);
 bool batch64_shape_supported(int bx, int by);
+int stage_wg_per_cu_fp64(int bx, int by);
+int stage_wg_per_cu_fp32(int bx, int by);
 bool batch32_shape_supported(int bx, int by);
 hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
                                    int bx, int by, int grid_cap, int total, hipStream_t st);
@@ -98,6 +100,48 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   t->tiles_j = (nj + t->tj - 1) / t->tj;
   int kc = (p && p->kchunk > 0) ? p->kchunk : 64;
   if (kc > nk) kc = nk;
+  t->kchunk = kc;
+  t->nchunks = (nk + kc - 1) / kc;
+  t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
+}
+
+// Planes per chunk when the caller leaves it to the library.  Every workgroup
+// marches kc + 2 planes (two warm-up planes), and the workgroups run in
+// rounds of `slots` (workgroups resident on the whole device), so a launch
+// costs about ceil(tiles * chunks / slots) * (kc + 2) plane steps.  The
+// chunk length minimising that count fills the last round instead of leaving
+// most CUs idle in it; ties go to the longer chunk (fewer halo re-reads).
+// Chunks are at least 8 planes (the partial-sum arrays are sized for that).
+int auto_kchunk(int tiles, int nk, long long slots) {
+  if (nk <= 8 || slots < 1) return nk < 64 ? nk : 64;
+  int best_kc = nk;
+  long long best = -1;
+  for (int c = 1; c <= (nk + 7) / 8; ++c) {
+    const int kc = (nk + c - 1) / c;
+    if (kc < 8) break;
+    const long long chunks = (nk + kc - 1) / kc;
+    const long long rounds = ((long long)tiles * chunks + slots - 1) / slots;
+    const long long cost = rounds * (kc + 2);
+    if (best < 0 || cost < best || (cost == best && kc > best_kc)) {
+      best = cost;
+      best_kc = kc;
+    }
+  }
+  return best_kc;
+}
+
+// pick_tiling, then (kchunk left to the library) the chunk length for the
+// current device's CU count and the shape's occupancy
+void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
+  pick_tiling(ni, nj, nk, p, t);
+  if (p && p->kchunk > 0) return;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
+  const int per_cu = (p && p->precision == JZ_FP32_FLUX) ? stage_wg_per_cu_fp32(t->bx, t->by)
+                                                          : stage_wg_per_cu_fp64(t->bx, t->by);
+  if (per_cu < 1 || ncu < 1) return;
+  const int kc = auto_kchunk(t->tiles_i * t->tiles_j, nk, (long long)per_cu * ncu);
   t->kchunk = kc;
   t->nchunks = (nk + kc - 1) / kc;
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
@@ -290,7 +334,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->N = (long long)ni * nj * nk;
   s->p = *p;
   s->ph = make_phys(*p);
-  pick_tiling(ni, nj, nk, p, &s->tl);
+  pick_tiling_for_device(ni, nj, nk, p, &s->tl);
   s->prec = p->precision;
   s->cap = partial_capacity(ni, nj, nk, s->tl);
   s->L = layout_for(s->N, s->tl, s->prec, s->cap);
@@ -689,7 +733,7 @@ int jz_set_tiling(jz_solver* s, int tile_i, int tile_j, int kchunk) {
   std::string why;
   if (!params_ok(&p, &why)) return fail(JZ_EINVAL, "jz_set_tiling: %s", why.c_str());
   Tiling t;
-  pick_tiling(s->ni, s->nj, s->nk, &p, &t);
+  pick_tiling_for_device(s->ni, s->nj, s->nk, &p, &t);
   if (t.nblocks > s->cap) return fail(JZ_EINVAL, "jz_set_tiling: %d tiles exceed the %d the workspace holds", t.nblocks, s->cap);
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->p = p;

@@ -34,6 +34,25 @@ hipError_t launch_stage_fp64(const StageArgs& a, const int* flag, int mode, int 
   return hipErrorInvalidValue;
 }
 
+// Workgroups of the given shape that fit on one CU at once (occupancy of the
+// middle-stage kernel, which the other stages of the shape match or exceed);
+// 0 if the runtime cannot tell.
+int stage_wg_per_cu_fp64(int bx, int by) {
+  int per_cu = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (bx == 32 && by == 16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 32, 16, 0>, 512, 0);
+  else if (bx == 64 && by == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 64, 8, 0>, 512, 0);
+  else if (bx == 16 && by == 32)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 16, 32, 0>, 512, 0);
+  else if (bx == 32 && by == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 32, 8, 0>, 256, 0);
+  else if (bx == 16 && by == 16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 16, 16, 0>, 256, 0);
+  return e == hipSuccess ? per_cu : 0;
+}
+
 // ---------------------------------------------------------------------------
 // persistent batch launches (FP64)
 // ---------------------------------------------------------------------------

@@ -39,6 +39,20 @@ hipError_t launch_stage_fp32(const StageArgs& a, const int* flag, int kind, int 
   return hipErrorInvalidValue;
 }
 
+// Workgroups of the given shape that fit on one CU at once (occupancy of the
+// middle-stage kernel); 0 if the runtime cannot tell.
+int stage_wg_per_cu_fp32(int bx, int by) {
+  int per_cu = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (bx == 32 && by == 16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<float, float, float, true, 32, 16, 0>, 512, 0);
+  else if (bx == 32 && by == 24)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<float, float, float, true, 32, 24, 0>, 768, 0);
+  else if (bx == 16 && by == 16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<float, float, float, true, 16, 16, 0>, 256, 0);
+  return e == hipSuccess ? per_cu : 0;
+}
+
 // ---------------------------------------------------------------------------
 // persistent batch launches (FP32-flux)
 // ---------------------------------------------------------------------------

@@ -396,6 +396,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 
     // ---- owned columns: in-plane terms of plane g, zeta face, residual of s ----
     if (isI) {
+      // Start the global reads the update of plane s needs (Q(0), and the
+      // metrics for the next-dt spectral radius) before the in-plane work,
+      // so that their latency overlaps it.
+      const long long ns = node(s);
+      constexpr bool Q0_IN_REGS = std::is_same<Rl, double>::value && std::is_same<TIn, double>::value;
+      double q0v[5] = {0, 0, 0, 0, 0};
+      double mo[10];
+      if (!WRITE_R && s >= kbeg) {
+        if (!(Q0_IN_REGS && q0_is_input)) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) q0v[v] = A.q0[5 * ns + v];
+        }
+      }
       Rl Rg[5];
       {
         // xi faces t-1/2 and t+1/2, eta faces t-BX/2 and t+BX/2
@@ -407,18 +420,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
         const Rl e2ym = k2 * fmax(sNy[c - BX], sNy[c]);
         const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
         const Rl sgyp = Rl(0.5) * (sSy[c] + sSy[c + BX]), sgym = Rl(0.5) * (sSy[c - BX] + sSy[c]);
+// One variable per trip (not unrolled: the unrolled form runs out of
+        // registers).  The results rotate through Rg so that no register is
+        // indexed by the trip count.
+        typedef __attribute__((address_space(3))) const Rl* lds_ptr;
 #pragma unroll 1
         for (int v = 0; v < 5; ++v) {
-          const Rl q0 = sQ[v][c];
-          const Rl qxp = sQ[v][c + 1], qxpp = sQ[v][c + 2], qxm = sQ[v][c - 1], qxmm = sQ[v][c - 2];
-          const Rl qyp = sQ[v][c + BX], qypp = sQ[v][c + 2 * BX], qym = sQ[v][c - BX], qymm = sQ[v][c - 2 * BX];
+          // The empty asm hides the array base, so that every neighbour
+          // access is one base register plus an immediate offset.
+          lds_ptr q = (lds_ptr)&sQ[v][c - 2 * BX];
+          asm volatile("" : "+v"(q));
+          lds_ptr fx = (lds_ptr)&sFx[v][c - 1];
+          asm volatile("" : "+v"(fx));
+          lds_ptr fy = (lds_ptr)&sFy[v][c - BX];
+          asm volatile("" : "+v"(fy));
+          const Rl q0 = q[2 * BX];
+          const Rl qxp = q[2 * BX + 1], qxpp = q[2 * BX + 2], qxm = q[2 * BX - 1], qxmm = q[2 * BX - 2];
+          const Rl qyp = q[3 * BX], qypp = q[4 * BX], qym = q[BX], qymm = q[0];
           const Rl dxp = sgxp * (e2xp * (qxp - q0) - e4xp * ((qxpp - qxm) - Rl(3) * (qxp - q0)));
           const Rl dxm = sgxm * (e2xm * (q0 - qxm) - e4xm * ((qxp - qxmm) - Rl(3) * (q0 - qxm)));
           const Rl dyp = sgyp * (e2yp * (qyp - q0) - e4yp * ((qypp - qym) - Rl(3) * (qyp - q0)));
           const Rl dym = sgym * (e2ym * (q0 - qym) - e4ym * ((qyp - qymm) - Rl(3) * (q0 - qym)));
-          const Rl cx = Rl(0.5) * (sFx[v][c + 1] - sFx[v][c - 1]);
-          const Rl cy = Rl(0.5) * (sFy[v][c + BX] - sFy[v][c - BX]);
-          Rg[v] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
+          const Rl cx = Rl(0.5) * (fx[2] - fx[0]);
+          const Rl cy = Rl(0.5) * (fy[2 * BX] - fy[0]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Rg[r] = Rg[r + 1];
+          Rg[4] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
         }
       }
       if (s >= kbeg - 1) {
@@ -433,7 +460,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
           Hp[v] = Rl(0.5) * (Fzs[v] + Fzg[v]) - sg * (e2 * (Qg[v] - Qs[v]) - e4 * d3);
         }
         if (s >= kbeg) {
-          const long long ns = node(s);
           double R[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) R[v] = Js * (double)(Rin[v] + (Hp[v] - Hm[v]));
@@ -444,19 +470,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
             double qn[5];
             // In the first stage the stencil input is Q(0) itself and, in the
             // FP64 form, the column registers hold it exactly: no re-read.
-            if (std::is_same<Rl, double>::value && std::is_same<TIn, double>::value && q0_is_input) {
+            if (Q0_IN_REGS && q0_is_input) {
 #pragma unroll
               for (int v = 0; v < 5; ++v) qn[v] = (double)Qs[v] - adt * R[v];
             } else {
 #pragma unroll
-              for (int v = 0; v < 5; ++v) qn[v] = A.q0[5 * ns + v] - adt * R[v];
+              for (int v = 0; v < 5; ++v) qn[v] = q0v[v] - adt * R[v];
             }
 #pragma unroll
             for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)qn[v];
             if (LAMMAX) {
-              double m[10];
-              met.load(ns, m, m[9]);
-              lmax = max_nan(lmax, lambda_sum(qn, m, ph.gamma));
+              met.load(ns, mo, mo[9]);
+              lmax = max_nan(lmax, lambda_sum(qn, mo, ph.gamma));
             }
           }
           if (NORMS) {
