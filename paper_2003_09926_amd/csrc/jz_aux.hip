@@ -1,5 +1,6 @@
 // jz_aux.hip -- metric computation, input validation, CFL reduction and the
 // per-step finalize kernel of the jet-LES library.
+#include <type_traits>
 #include "jz_internal.h"
 
 namespace jz {
@@ -153,10 +154,11 @@ __global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restric
   __shared__ double red[256];
   double mx = 0.0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
-    double qq[5], mm[10];
+    double qq[5], mJ;
+    typename std::conditional<MET32, float, double>::type mm[9];
     for (int c = 0; c < 5; ++c) qq[c] = q[5 * n + c];
-    met.load(n, mm, mm[9]);
-    mx = max_nan(mx, lambda_sum(qq, mm, gamma));
+    met.load(n, mm, mJ);
+    mx = max_nan(mx, lambda_sum(qq, mm, mJ, gamma));
   }
   red[threadIdx.x] = mx;
   __syncthreads();

@@ -94,21 +94,59 @@ __host__ __device__ inline int wrap_index(int i, int n) {
 // NaN-propagating maximum (a plain fmax would drop a NaN).
 __device__ inline double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }
 
+// FP64 reciprocal and square root for positive, normal arguments: hardware
+// seed refined by Newton (reciprocal) and Goldschmidt (square root)
+// iterations to full double precision.  Non-positive or non-finite inputs
+// give NaN/Inf, which the norm and dt checks then report.
+__device__ inline double rcp_pos(double y) {
+  double r = __builtin_amdgcn_rcp(y);
+  double e = fma(-y, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-y, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ inline double div_pos(double x, double y) {
+  const double r = rcp_pos(y);
+  const double q = x * r;
+  return fma(fma(-y, q, x), r, q);
+}
+
+__device__ inline double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// FP32 counterparts: hardware approximations (about 1 ulp), which is the
+// accuracy the FP32-flux form works at
+__device__ inline float rcp_pos(float y) { return __builtin_amdgcn_rcpf(y); }
+__device__ inline float div_pos(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+__device__ inline float sqrt_pos(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // sum_d lambda^d at one node: |J S^d . u| + a J |S^d|, the inviscid spectral
-// radii in index units that set the CFL time step.
-__device__ inline double lambda_sum(const double q[5], const double m[10], double gamma) {
-  const double rinv = 1.0 / q[0];
+// radii in index units that set the CFL time step.  The nine scaled metrics
+// come in their stored type (double, or float in the FP32-flux form) and are
+// widened here, so every caller computes the same double result.
+template <typename M>
+__device__ inline double lambda_sum(const double q[5], const M s[9], double J, double gamma) {
+  const double rinv = rcp_pos(q[0]);
   const double u = q[1] * rinv, v = q[2] * rinv, w = q[3] * rinv;
   const double p = (gamma - 1.0) * (q[4] - 0.5 * q[0] * (u * u + v * v + w * w));
-  const double a = sqrt(gamma * p * rinv);
-  const double J = m[9];
-  double s = 0.0;
+  const double a = sqrt_pos(gamma * p * rinv);
+  double sum = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double sx = m[3 * d], sy = m[3 * d + 1], sz = m[3 * d + 2];
-    s += fabs(J * (sx * u + sy * v + sz * w)) + a * J * sqrt(sx * sx + sy * sy + sz * sz);
+    const double sx = (double)s[3 * d], sy = (double)s[3 * d + 1], sz = (double)s[3 * d + 2];
+    sum += fabs(J * (sx * u + sy * v + sz * w)) + a * J * sqrt_pos(sx * sx + sy * sy + sz * sz);
   }
-  return s;
+  return sum;
 }
 
 // Metric views: load the nine scaled metrics of node n in the compute type

@@ -60,42 +60,6 @@ struct Prim {
   Rl u, v, w, T, p;
 };
 
-// FP64 reciprocal and square root for positive, normal arguments: hardware
-// seed refined by Newton (reciprocal) and Goldschmidt (square root)
-// iterations to full double precision.  Non-positive or non-finite inputs
-// give NaN/Inf, which the norm and dt checks then report.
-__device__ inline double rcp_pos(double y) {
-  double r = __builtin_amdgcn_rcp(y);
-  double e = fma(-y, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-y, r, 1.0);
-  return fma(r, e, r);
-}
-
-__device__ inline double div_pos(double x, double y) {
-  const double r = rcp_pos(y);
-  const double q = x * r;
-  return fma(fma(-y, q, x), r, q);
-}
-
-__device__ inline double sqrt_pos(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  const double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
-  return fma(d, h, g);
-}
-
-// FP32 counterparts: hardware approximations (about 1 ulp), which is the
-// accuracy the FP32-flux form works at
-__device__ inline float rcp_pos(float y) { return __builtin_amdgcn_rcpf(y); }
-__device__ inline float div_pos(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
-__device__ inline float sqrt_pos(float x) { return __builtin_amdgcn_sqrtf(x); }
-
 template <typename Rl>
 __device__ inline Prim<Rl> primitives(const Rl q[5], Rl gm1, Rl gamma) {
   Prim<Rl> r;
@@ -250,7 +214,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   Rl Qm[5], Qs[5], Qg[5], Ql[5];
   Rl nus = 0, sigs = 0;
   double Js = 0.0;
-  Rl Fzs[5] = {0, 0, 0, 0, 0}, Hm[5] = {0, 0, 0, 0, 0}, Rin[5] = {0, 0, 0, 0, 0};
+  // Acc carries, from one march step to the next, the in-plane terms of the
+  // next plane to be written minus the zeta face flux below it
+  Rl Fzs[5] = {0, 0, 0, 0, 0}, Acc[5] = {0, 0, 0, 0, 0};
   double nsum[5] = {0, 0, 0, 0, 0}, nmax[5] = {0, 0, 0, 0, 0};
   double lmax = 0.0;
 
@@ -392,24 +358,40 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       sNy[c] = sensor(Pg[4][c - BX], p, Pg[4][c + BX]);
       nug = sensor(sPr[slot_s][4][c], p, sPr[slot_l][4][c]);
     }
-    __syncthreads();
 
-    // ---- owned columns: in-plane terms of plane g, zeta face, residual of s ----
-    if (isI) {
-      // Start the global reads the update of plane s needs (Q(0), and the
-      // metrics for the next-dt spectral radius) before the in-plane work,
-      // so that their latency overlaps it.
-      const long long ns = node(s);
-      constexpr bool Q0_IN_REGS = std::is_same<Rl, double>::value && std::is_same<TIn, double>::value;
-      double q0v[5] = {0, 0, 0, 0, 0};
-      double mo[10];
+    // ---- owned columns, before the barrier: the zeta face between planes s
+    // and s+1 needs only the column's registers, and the global reads for the
+    // update of plane s (Q(0); the metrics for the next-dt spectral radius)
+    // are started here so that their latency overlaps the in-plane work.
+    const bool own = isI && s >= kbeg - 1;  // plane kbeg-1 is not written
+    const long long ns = node(s);
+    constexpr bool Q0_IN_REGS = std::is_same<Rl, double>::value && std::is_same<TIn, double>::value;
+    double q0v[5] = {0, 0, 0, 0, 0};
+    typename std::conditional<MET32, float, double>::type mo[9];
+    double moJ = 0.0;
+    Rl Hp[5] = {0, 0, 0, 0, 0};
+    if (own) {
       if (!WRITE_R && s >= kbeg) {
         if (!(Q0_IN_REGS && q0_is_input)) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) q0v[v] = A.q0[5 * ns + v];
         }
+        if (LAMMAX) met.load(ns, mo, moJ);
       }
-      Rl Rg[5];
+      const Rl e2 = k2 * fmax(nus, nug);
+      const Rl e4 = fmax(Rl(0), k4 - e2);
+      const Rl sg = Rl(0.5) * (sigs + sigg);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const Rl d3 = (Ql[v] - Qm[v]) - Rl(3) * (Qg[v] - Qs[v]);
+        Hp[v] = Rl(0.5) * (Fzs[v] + Fzg[v]) - sg * (e2 * (Qg[v] - Qs[v]) - e4 * d3);
+      }
+    }
+    __syncthreads();
+
+    // ---- owned columns: in-plane terms of plane g, residual of plane s ------
+    if (own) {
+      Rl Rg[5] = {0, 0, 0, 0, 0};
       {
         // xi faces t-1/2 and t+1/2, eta faces t-BX/2 and t+BX/2
         const Rl e2xp = k2 * fmax(sNx[c], sNx[c + 1]);
@@ -420,7 +402,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
         const Rl e2ym = k2 * fmax(sNy[c - BX], sNy[c]);
         const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
         const Rl sgyp = Rl(0.5) * (sSy[c] + sSy[c + BX]), sgym = Rl(0.5) * (sSy[c - BX] + sSy[c]);
-// One variable per trip (not unrolled: the unrolled form runs out of
+        // One variable per trip (not unrolled: the unrolled form runs out of
         // registers).  The results rotate through Rg so that no register is
         // indexed by the trip count.
         typedef __attribute__((address_space(3))) const Rl* lds_ptr;
@@ -448,55 +430,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
           Rg[4] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
         }
       }
-      if (s >= kbeg - 1) {
-        // zeta face between planes s and s+1
-        const Rl e2 = k2 * fmax(nus, nug);
-        const Rl e4 = fmax(Rl(0), k4 - e2);
-        const Rl sg = Rl(0.5) * (sigs + sigg);
-        Rl Hp[5];
+      if (s >= kbeg) {
+        double R[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const Rl d3 = (Ql[v] - Qm[v]) - Rl(3) * (Qg[v] - Qs[v]);
-          Hp[v] = Rl(0.5) * (Fzs[v] + Fzg[v]) - sg * (e2 * (Qg[v] - Qs[v]) - e4 * d3);
-        }
-        if (s >= kbeg) {
-          double R[5];
+        for (int v = 0; v < 5; ++v) R[v] = Js * (double)(Acc[v] + Hp[v]);
+        if (WRITE_R) {
 #pragma unroll
-          for (int v = 0; v < 5; ++v) R[v] = Js * (double)(Rin[v] + (Hp[v] - Hm[v]));
-          if (WRITE_R) {
+          for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)R[v];
+        } else {
+          double qn[5];
+          // In the first stage the stencil input is Q(0) itself and, in the
+          // FP64 form, the column registers hold it exactly: no re-read.
+          if (Q0_IN_REGS && q0_is_input) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)R[v];
+            for (int v = 0; v < 5; ++v) qn[v] = (double)Qs[v] - adt * R[v];
           } else {
-            double qn[5];
-            // In the first stage the stencil input is Q(0) itself and, in the
-            // FP64 form, the column registers hold it exactly: no re-read.
-            if (Q0_IN_REGS && q0_is_input) {
 #pragma unroll
-              for (int v = 0; v < 5; ++v) qn[v] = (double)Qs[v] - adt * R[v];
-            } else {
-#pragma unroll
-              for (int v = 0; v < 5; ++v) qn[v] = q0v[v] - adt * R[v];
-            }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)qn[v];
-            if (LAMMAX) {
-              met.load(ns, mo, mo[9]);
-              lmax = max_nan(lmax, lambda_sum(qn, mo, ph.gamma));
-            }
+            for (int v = 0; v < 5; ++v) qn[v] = q0v[v] - adt * R[v];
           }
-          if (NORMS) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-              nsum[v] += R[v] * R[v];
-              nmax[v] = max_nan(nmax[v], fabs(R[v]));
-            }
+          for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)qn[v];
+          if (LAMMAX) lmax = max_nan(lmax, lambda_sum(qn, mo, moJ, ph.gamma));
+        }
+        if (NORMS) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            nsum[v] += R[v] * R[v];
+            nmax[v] = max_nan(nmax[v], fabs(R[v]));
           }
         }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Hm[v] = Hp[v];
       }
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Rin[v] = Rg[v];
+      for (int v = 0; v < 5; ++v) Acc[v] = Rg[v] - Hp[v];
     }
 
     // ---- shift the column registers and the ring by one plane ---------------
@@ -554,9 +519,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 }
 
 
+// Waves per SIMD the register allocation must allow: the FP32-flux stages fit
+// three (at most 168 VGPRs) except the single-stage form, which carries both
+// reductions; FP64 leaves it to the compiler (two fit).
+template <typename Rl, int MODE>
+constexpr int stage_waves_per_eu() { return (sizeof(Rl) == 4 && MODE != 3) ? 3 : 1; }
+
 // Single block: one workgroup per tile, tiles spread XCD by XCD.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>())))
+void stage_kernel(StageArgs A, const int* __restrict__ flag) {
   if (*flag) return;  // a failed step froze the state
   stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -568,7 +540,8 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageArgs A, const int* _
 // L2; the workgroups of a slot walk its share with a fixed stride, and every
 // workgroup exits once its share is done.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>())))
+void stage_batch_kernel(const BlockDesc* __restrict__ desc,
                                                              const int* __restrict__ tile_off, int nblk,
                                                              int stage, int nstages, double alpha) {
   // at most 8 slots, and never more slots than workgroups, so that every
