@@ -1,6 +1,6 @@
 /* jetles.h -- C ABI of the MI355X jet-LES hot path.
  *
- * One solver object owns one structured, periodic, curvilinear block of
+ * One solver object owns one structured curvilinear block of
  * ni x nj x nk nodes (xi = i streamwise, eta = j, zeta = k) resident in the
  * HBM of one GPU, and advances the filtered compressible Navier-Stokes
  * equations (Sec. 3 of arXiv:2003.09926, Eq. (les) with the closure of
@@ -19,8 +19,9 @@
  *   - a metric set is 10 x N doubles: m[(3 d + a) * N + n] = S^d_a, the
  *     derivative of xi_d with respect to x_a divided by J, for d, a in
  *     {0, 1, 2}; m[9 * N + n] = J = 1 / det d(x, y, z) / d(xi, eta, zeta);
- *   - the block is periodic in all three directions (the periodic wrap
- *     stands in for the neighbour ranks' ghost layers of Sec. 4.3);
+ *   - each direction is periodic (the wrap stands in for the neighbour
+ *     ranks' ghost layers of Sec. 4.3) unless jz_params.bc gives its two
+ *     faces physical boundary conditions (see jz_bc);
  *   - units: ambient rho = 1, p = 1/gamma, sound speed 1, jet diameter 1,
  *     mu_inf = mach_j / re_d, Sutherland reference temperature 1;
  *   - every function returns an int status (JZ_OK = 0, negative = error) and
@@ -52,6 +53,28 @@ typedef struct jz_solver jz_solver; /* opaque, library-owned */
 
 typedef enum { JZ_FP64 = 0, JZ_FP32_FLUX = 1 } jz_precision;
 
+/* Boundary types of the six faces, indexed xi-, xi+, eta-, eta+, zeta-,
+ * zeta+ in jz_params.bc (Sec. 3, boundary conditions).  A direction is
+ * either periodic at both faces or bounded at both.  Along a bounded
+ * direction (at least 5 nodes) the two outermost node layers at each end are
+ * boundary layers: the residual advances only the nodes between them, and
+ * after every Runge-Kutta stage the layers are set by their face's rule --
+ *   JZ_BC_INFLOW:   supersonic inflow (the jet exit): the layer keeps the
+ *                   state it was given by jz_set_state;
+ *   JZ_BC_FARFIELD: far field from Riemann invariants: the state of the
+ *                   first interior node along the face normal (index 2, or
+ *                   n-3) and the free stream (rho = 1, u = (mach_inf, 0, 0),
+ *                   p = 1/gamma) give the outgoing and incoming invariants
+ *                   u_n +- 2a/(gamma-1); entropy and tangential velocity come
+ *                   from the upwind side; a supersonic normal flow takes all
+ *                   values from its upwind side.  Both layers get that state.
+ * A node in the layers of an inflow face is always held; otherwise the
+ * bounded directions are processed in the order xi, eta, zeta, so a node in
+ * the layers of several directions keeps the last one's value.  Residual
+ * norms and the CFL maximum run over the advanced nodes only; jz_eval_residual
+ * returns 0 on boundary layers.  Batches take periodic blocks only. */
+typedef enum { JZ_BC_PERIODIC = 0, JZ_BC_INFLOW = 1, JZ_BC_FARFIELD = 2 } jz_bc;
+
 /* Physical and numerical parameters.  Values the paper leaves open carry the
  * defaults of jz_params_default(); the paper fixes Pr = 0.72 (Sec. 3) and the
  * number of stages (5, Sec. 3). */
@@ -73,6 +96,9 @@ typedef struct {
   int tile_i, tile_j;  /* launch shape of the stage kernel; 0 = library default */
   int kchunk;          /* planes marched per workgroup; 0 = chosen by the library for
                           the current device (fills the last round of workgroups) */
+  int bc[6];           /* jz_bc of the faces xi-, xi+, eta-, eta+, zeta-, zeta+ (all periodic) */
+  double mach_inf;     /* free-stream velocity along x of the far field, in ambient
+                          sound speeds (0) */
 } jz_params;
 
 /* Fill *p with the defaults listed above. */
@@ -96,8 +122,9 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
  * the periodic shift vectors period[3 d + a] (the change of coordinate a when
  * index d wraps once forwards).  Computes the Thomas-Lombard metric set and J
  * on the GPU in FP64 (Sec. 3: curvilinear form; Sec. 4.2: metrics computed
- * once after the mesh is read).  JZ_EINVAL if any J is non-positive or not
- * finite.  Synchronises. */
+ * once after the mesh is read).  Along a bounded direction the shifts are
+ * ignored and the differences at its two end nodes are one-sided.  JZ_EINVAL
+ * if any J is non-positive or not finite.  Synchronises. */
 int jz_set_grid_coords(jz_solver* s, const double* x, const double* y, const double* z,
                        const double* period);
 

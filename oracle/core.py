@@ -38,12 +38,17 @@ class Params(ctypes.Structure):
                 ("cs", ctypes.c_double), ("k2", ctypes.c_double), ("k4", ctypes.c_double),
                 ("tv_alpha", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("dt_fixed", ctypes.c_double), ("rk_alpha", ctypes.c_double * 5),
-                ("n_stages", ctypes.c_int)]
+                ("n_stages", ctypes.c_int), ("bc", ctypes.c_int * 6), ("mach_inf", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "rk_alpha"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("rk_alpha", "bc")}
         d["rk_alpha"] = list(self.rk_alpha)
+        d["bc"] = list(self.bc)
         return d
+
+
+# boundary types of the faces (xi-, xi+, eta-, eta+, zeta-, zeta+)
+BC_PERIODIC, BC_INFLOW, BC_FARFIELD = 0, 1, 2
 
 
 _lib = None
@@ -60,13 +65,15 @@ def _load():
         i = ctypes.c_int
         lib.jzo_params_default.argtypes = [pp]
         lib.jzo_metrics_tl.argtypes = [i, i, i, dp, dp, dp, dp, dp]
+        lib.jzo_metrics_tl_bc.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int), dp]
+        lib.jzo_apply_bc.argtypes = [i, i, i, pp, dp, dp, dp]
         lib.jzo_residual.argtypes = [i, i, i, pp, dp, dp, dp]
         lib.jzo_fields.argtypes = [i, i, i, pp, dp, dp, dp, dp, dp, dp, dp, dp]
         lib.jzo_cfl_dt.argtypes = [i, i, i, pp, dp, dp, dp, dp]
         lib.jzo_step.argtypes = [i, i, i, pp, dp, dp, ctypes.c_double, dp, dp, dp]
         lib.jzo_advance.argtypes = [i, i, i, pp, dp, dp, i, dp, dp, dp]
-        for f in (lib.jzo_params_default, lib.jzo_metrics_tl, lib.jzo_residual, lib.jzo_fields,
-                  lib.jzo_cfl_dt, lib.jzo_step, lib.jzo_advance):
+        for f in (lib.jzo_params_default, lib.jzo_metrics_tl, lib.jzo_metrics_tl_bc, lib.jzo_apply_bc,
+                  lib.jzo_residual, lib.jzo_fields, lib.jzo_cfl_dt, lib.jzo_step, lib.jzo_advance):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -86,6 +93,9 @@ def default_params(**kw) -> Params:
         if k == "rk_alpha":
             for s in range(5):
                 p.rk_alpha[s] = v[s] if s < len(v) else 0.0
+        elif k == "bc":
+            for f in range(6):
+                p.bc[f] = int(v[f])
         else:
             if not hasattr(p, k):
                 raise KeyError(k)
@@ -97,12 +107,17 @@ def _c(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def metrics_tl(ni, nj, nk, x, y, z, period) -> np.ndarray:
-    """Thomas-Lombard metric set (10 x N) from node coordinates."""
+def metrics_tl(ni, nj, nk, x, y, z, period, bc=None) -> np.ndarray:
+    """Thomas-Lombard metric set (10 x N) from node coordinates; bc (six face
+    types) makes the directions with physical faces one-sided at their ends."""
     x, y, z = _c(x), _c(y), _c(z)
     per = _c(np.asarray(period, dtype=np.float64).reshape(9))
     m = np.empty((10, ni * nj * nk))
-    rc = _load().jzo_metrics_tl(ni, nj, nk, _ptr(x), _ptr(y), _ptr(z), _ptr(per), _ptr(m))
+    if bc is None:
+        rc = _load().jzo_metrics_tl(ni, nj, nk, _ptr(x), _ptr(y), _ptr(z), _ptr(per), _ptr(m))
+    else:
+        cb = (ctypes.c_int * 6)(*[int(t) for t in bc])
+        rc = _load().jzo_metrics_tl_bc(ni, nj, nk, _ptr(x), _ptr(y), _ptr(z), _ptr(per), cb, _ptr(m))
     if rc:
         raise ValueError(f"jzo_metrics_tl failed ({rc})")
     return m
@@ -171,3 +186,15 @@ def advance(dims, params: Params, m, q, nsteps: int):
     if rc:
         raise ValueError(f"jzo_advance failed ({rc})")
     return qn, t.value, rms, linf
+
+
+def apply_bc(dims, params: Params, m, q, q0) -> np.ndarray:
+    """The boundary conditions alone: returns q with its boundary layers set
+    (inflow layers from q0, far-field layers from q's first interior nodes)."""
+    ni, nj, nk = dims
+    m, q0 = _c(m), _c(q0)
+    qn = np.array(q, dtype=np.float64, order="C", copy=True)
+    rc = _load().jzo_apply_bc(ni, nj, nk, ctypes.byref(params), _ptr(m), _ptr(qn), _ptr(q0))
+    if rc:
+        raise ValueError(f"jzo_apply_bc failed ({rc})")
+    return qn

@@ -19,6 +19,8 @@
 //   * explicit five-stage Runge-Kutta, full residual in
 //     every stage                                          Sec. 3; Sec. 4.2 and its flow chart
 //   * five-point dissipation stencil, two ghost layers     Sec. 4.3
+//   * physical boundaries: supersonic inflow at the jet
+//     exit, far field from Riemann invariants              Sec. 3, boundary conditions
 // Points the paper leaves open (subgrid closure, dissipation constants, RK
 // coefficients, time-step rule, viscous stencil, metric form, scales) follow
 // the readings listed with the design notes; each is a field of jzo_params.
@@ -27,7 +29,10 @@
 // closed forms and invariants in tests/test_oracle_pins.py (free-stream
 // preservation, discrete conservation, isentropic vortex, second-order
 // convergence, shear-wave and entropy-wave decay factors, Smagorinsky closed
-// form, mirror symmetry).  The numerical values of the open constants are
+// form, mirror symmetry) and the boundary treatment in
+// tests/test_oracle_bc_pins.py (Riemann-invariant identities, free-stream
+// preservation and conservation on bounded blocks, transparency to an
+// outgoing acoustic pulse).  The numerical values of the open constants are
 // "parity unpinned" against the paper, which prints none.
 #include <cmath>
 #include <cstddef>
@@ -52,6 +57,10 @@ typedef struct {
   double dt_fixed;     // > 0: use this time step instead of the CFL rule
   double rk_alpha[5];  // stage coefficients Q(k) = Q(0) - a_k dt R(Q(k-1))
   int n_stages;
+  // boundary type of the faces xi-, xi+, eta-, eta+, zeta-, zeta+:
+  // 0 periodic, 1 supersonic inflow (state held), 2 far field (Riemann invariants)
+  int bc[6];
+  double mach_inf;     // far-field stream velocity along x, in ambient sound speeds
 } jzo_params;
 
 int jzo_params_default(jzo_params* p) {
@@ -74,6 +83,8 @@ int jzo_params_default(jzo_params* p) {
   p->rk_alpha[3] = 1.0 / 2.0;
   p->rk_alpha[4] = 1.0;
   p->n_stages = 5;
+  for (int f = 0; f < 6; ++f) p->bc[f] = 0;
+  p->mach_inf = 0.0;
   return 0;
 }
 
@@ -81,20 +92,43 @@ int jzo_params_default(jzo_params* p) {
 
 namespace {
 
+// A block is periodic along each direction unless its faces there carry
+// physical boundaries; then the two outermost node layers at each end are
+// boundary layers (set by the boundary conditions, never advanced by the
+// residual) and the nodes between them are the interior.
 struct Block {
   int n[3];
   long N;
-  Block(int ni, int nj, int nk) {
+  bool bnd[3];  // direction bounded by physical faces
+  Block(int ni, int nj, int nk, const int* bc = nullptr) {
     n[0] = ni; n[1] = nj; n[2] = nk;
     N = (long)ni * nj * nk;
+    for (int d = 0; d < 3; ++d) bnd[d] = bc && bc[2 * d] != 0;
   }
   static int wrap(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;
   }
-  // periodic linear index of logical node (i, j, k)
+  // index along d: periodic wrap, or clamped to the block along a bounded
+  // direction (only reached by stencils of boundary-layer nodes, whose
+  // residual is never used)
+  int idx(int i, int d) const {
+    if (!bnd[d]) return wrap(i, n[d]);
+    return i < 0 ? 0 : (i >= n[d] ? n[d] - 1 : i);
+  }
   long at(int i, int j, int k) const {
-    return wrap(i, n[0]) + (long)n[0] * (wrap(j, n[1]) + (long)n[1] * wrap(k, n[2]));
+    return idx(i, 0) + (long)n[0] * (idx(j, 1) + (long)n[1] * idx(k, 2));
+  }
+  bool interior(int i, int j, int k) const {
+    const int c[3] = {i, j, k};
+    for (int d = 0; d < 3; ++d)
+      if (bnd[d] && (c[d] < 2 || c[d] > n[d] - 3)) return false;
+    return true;
+  }
+  long n_interior() const {
+    long r = 1;
+    for (int d = 0; d < 3; ++d) r *= bnd[d] ? n[d] - 4 : n[d];
+    return r;
   }
   // linear index of the neighbour `off` steps along direction d
   long nb(int i, int j, int k, int d, int off) const {
@@ -127,34 +161,39 @@ struct Coords {
   }
 };
 
-// centred difference of coordinate a along d at logical node c
-static double dcoord(const Coords& C, int a, const int c[3], int d) {
+// Difference of a node function g along d at logical node c: centred, or
+// one-sided (first order) at the end nodes of a bounded direction, where
+// the centred stencil would leave the block.
+template <class G>
+static double diff(const Block& b, const G& g, const int c[3], int d) {
   int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+  if (b.bnd[d] && c[d] == 0) {
+    cp[d] += 1;
+    return g(cp) - g(c);
+  }
+  if (b.bnd[d] && c[d] == b.n[d] - 1) {
+    cm[d] -= 1;
+    return g(c) - g(cm);
+  }
   cp[d] += 1;
   cm[d] -= 1;
-  return 0.5 * (C.get(a, cp) - C.get(a, cm));
+  return 0.5 * (g(cp) - g(cm));
 }
-
-}  // namespace
-
-extern "C" {
 
 // Thomas-Lombard conservative metrics,
 //   S^d_a = delta_d2( x_a2 delta_d1 x_a1 ) - delta_d1( x_a2 delta_d2 x_a1 )
 // with (d, d1, d2) and (a, a1, a2) cyclic, x_a2 taken relative to the centre
 // node (an exact identity that limits roundoff); J^-1 = det of the matrix of
-// centred coordinate differences.  Output m[3 d + a] = S^d_a, m[9] = J.
-int jzo_metrics_tl(int ni, int nj, int nk, const double* x, const double* y, const double* z,
-                   const double* period9, double* m) {
-  if (ni < 1 || nj < 1 || nk < 1 || !x || !y || !z || !period9 || !m) return -1;
-  Block b(ni, nj, nk);
-  Coords C{b, {x, y, z}, {{0}}};
+// coordinate differences.  Output m[3 d + a] = S^d_a, m[9] = J.  Along a
+// bounded direction the differences at the two end nodes are one-sided.
+static void metrics_tl(const Block& b, const double* const X[3], const double* period9, double* m) {
+  Coords C{b, {X[0], X[1], X[2]}, {{0}}};
   for (int d = 0; d < 3; ++d)
-    for (int a = 0; a < 3; ++a) C.P[d][a] = period9[3 * d + a];
+    for (int a = 0; a < 3; ++a) C.P[d][a] = b.bnd[d] ? 0.0 : period9[3 * d + a];
 #pragma omp parallel for schedule(static)
-  for (int k = 0; k < nk; ++k)
-    for (int j = 0; j < nj; ++j)
-      for (int i = 0; i < ni; ++i) {
+  for (int k = 0; k < b.n[2]; ++k)
+    for (int j = 0; j < b.n[1]; ++j)
+      for (int i = 0; i < b.n[0]; ++i) {
         const int c[3] = {i, j, k};
         const long p = b.at(i, j, k);
         for (int d = 0; d < 3; ++d) {
@@ -162,32 +201,48 @@ int jzo_metrics_tl(int ni, int nj, int nk, const double* x, const double* y, con
           for (int a = 0; a < 3; ++a) {
             const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
             const double xc = C.get(a2, c);
-            double t1, t2;
-            {  // delta_d2( (x_a2 - xc) delta_d1 x_a1 )
-              int cp[3] = {i, j, k}, cm[3] = {i, j, k};
-              cp[d2] += 1;
-              cm[d2] -= 1;
-              t1 = 0.5 * ((C.get(a2, cp) - xc) * dcoord(C, a1, cp, d1) -
-                          (C.get(a2, cm) - xc) * dcoord(C, a1, cm, d1));
-            }
-            {  // delta_d1( (x_a2 - xc) delta_d2 x_a1 )
-              int cp[3] = {i, j, k}, cm[3] = {i, j, k};
-              cp[d1] += 1;
-              cm[d1] -= 1;
-              t2 = 0.5 * ((C.get(a2, cp) - xc) * dcoord(C, a1, cp, d2) -
-                          (C.get(a2, cm) - xc) * dcoord(C, a1, cm, d2));
-            }
-            m[(3 * d + a) * b.N + p] = t1 - t2;
+            auto xa1 = [&](const int* e) { return C.get(a1, e); };
+            auto h1 = [&](const int* e) { return (C.get(a2, e) - xc) * diff(b, xa1, e, d1); };
+            auto h2 = [&](const int* e) { return (C.get(a2, e) - xc) * diff(b, xa1, e, d2); };
+            m[(3 * d + a) * b.N + p] = diff(b, h1, c, d2) - diff(b, h2, c, d1);
           }
         }
         double M[3][3];  // M[a][d] = d x_a / d xi_d
-        for (int a = 0; a < 3; ++a)
-          for (int d = 0; d < 3; ++d) M[a][d] = dcoord(C, a, c, d);
+        for (int a = 0; a < 3; ++a) {
+          auto xa = [&](const int* e) { return C.get(a, e); };
+          for (int d = 0; d < 3; ++d) M[a][d] = diff(b, xa, c, d);
+        }
         const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
                            M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
                            M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
         m[9 * b.N + p] = 1.0 / det;
       }
+}
+
+}  // namespace
+
+extern "C" {
+
+int jzo_metrics_tl(int ni, int nj, int nk, const double* x, const double* y, const double* z,
+                   const double* period9, double* m) {
+  if (ni < 1 || nj < 1 || nk < 1 || !x || !y || !z || !period9 || !m) return -1;
+  Block b(ni, nj, nk);
+  const double* X[3] = {x, y, z};
+  metrics_tl(b, X, period9, m);
+  return 0;
+}
+
+// The same on a block whose faces carry the boundary types bc[6] (see
+// jzo_params): directions with physical faces get one-sided end differences.
+int jzo_metrics_tl_bc(int ni, int nj, int nk, const double* x, const double* y, const double* z,
+                      const double* period9, const int* bc, double* m) {
+  if (ni < 1 || nj < 1 || nk < 1 || !x || !y || !z || !period9 || !m || !bc) return -1;
+  const int n[3] = {ni, nj, nk};
+  for (int d = 0; d < 3; ++d)
+    if ((bc[2 * d] != 0) != (bc[2 * d + 1] != 0) || (bc[2 * d] != 0 && n[d] < 5)) return -1;
+  Block b(ni, nj, nk, bc);
+  const double* X[3] = {x, y, z};
+  metrics_tl(b, X, period9, m);
   return 0;
 }
 
@@ -339,6 +394,10 @@ static void residual(const Block& b, const jzo_params& P, const double* m, const
     for (int j = 0; j < b.n[1]; ++j)
       for (int i = 0; i < b.n[0]; ++i) {
         const long n = b.at(i, j, k);
+        if (!b.interior(i, j, k)) {  // boundary layers carry no residual
+          for (int v = 0; v < 5; ++v) r[v * N + n] = 0.0;
+          continue;
+        }
         double C[5] = {0, 0, 0, 0, 0}, D[5] = {0, 0, 0, 0, 0};
         for (int d = 0; d < 3; ++d) {
           const long np1 = b.nb(i, j, k, d, +1), nm1 = b.nb(i, j, k, d, -1);
@@ -369,28 +428,134 @@ static void residual(const Block& b, const jzo_params& P, const double* m, const
 }
 
 static double cfl_max(const Block& b, const double* m, const double* q, const jzo_params& P) {
-  // max over nodes of lambda^xi + lambda^eta + lambda^zeta (inviscid)
+  // max over the interior nodes of lambda^xi + lambda^eta + lambda^zeta (inviscid)
   const long N = b.N;
   double mx = 0.0;
 #pragma omp parallel for reduction(max : mx) schedule(static)
-  for (long n = 0; n < N; ++n) {
-    const double rho = q[n];
-    const double u = q[N + n] / rho, v = q[2 * N + n] / rho, w = q[3 * N + n] / rho;
-    const double p = (P.gamma - 1.0) * (q[4 * N + n] - 0.5 * rho * (u * u + v * v + w * w));
-    const double a = std::sqrt(P.gamma * p / rho);
-    const double J = m[9 * N + n];
-    double s = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      const double sx = m[(3 * d) * N + n], sy = m[(3 * d + 1) * N + n], sz = m[(3 * d + 2) * N + n];
-      s += std::fabs(J * (sx * u + sy * v + sz * w)) + a * std::fabs(J) * std::sqrt(sx * sx + sy * sy + sz * sz);
-    }
-    mx = std::max(mx, s);
-  }
+  for (int k = 0; k < b.n[2]; ++k)
+    for (int j = 0; j < b.n[1]; ++j)
+      for (int i = 0; i < b.n[0]; ++i) {
+        if (!b.interior(i, j, k)) continue;
+        const long n = b.at(i, j, k);
+        const double rho = q[n];
+        const double u = q[N + n] / rho, v = q[2 * N + n] / rho, w = q[3 * N + n] / rho;
+        const double p = (P.gamma - 1.0) * (q[4 * N + n] - 0.5 * rho * (u * u + v * v + w * w));
+        const double a = std::sqrt(P.gamma * p / rho);
+        const double J = m[9 * N + n];
+        double sum = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          const double sx = m[(3 * d) * N + n], sy = m[(3 * d + 1) * N + n], sz = m[(3 * d + 2) * N + n];
+          sum += std::fabs(J * (sx * u + sy * v + sz * w)) + a * std::fabs(J) * std::sqrt(sx * sx + sy * sy + sz * sz);
+        }
+        mx = std::max(mx, sum);
+      }
   return mx;
 }
 
+// Far-field state from Riemann invariants of the one-dimensional flow normal
+// to the boundary (outward unit normal nh): the outgoing invariant
+// R+ = u_n + 2a/(gamma-1) comes from the interior state qi, the incoming
+// R- = u_n - 2a/(gamma-1) from the free stream; their half sum and difference
+// give the normal velocity and sound speed at the boundary.  Entropy p/rho^gamma
+// and the tangential velocity come from the upwind side (interior on outflow,
+// free stream on inflow).  A supersonic normal flow takes every quantity
+// from its upwind side.  Free stream: rho = 1, u = (mach_inf, 0, 0), p = 1/gamma.
+static void farfield_state(const jzo_params& P, const double qi[5], const double nh[3], double qb[5]) {
+  const double g = P.gamma;
+  const double ri = qi[0];
+  const double ui[3] = {qi[1] / ri, qi[2] / ri, qi[3] / ri};
+  const double pi = (g - 1.0) * (qi[4] - 0.5 * ri * (ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2]));
+  const double ai = std::sqrt(g * pi / ri);
+  const double re = 1.0, pe = 1.0 / g, ae = 1.0;
+  const double ue[3] = {P.mach_inf, 0.0, 0.0};
+  const double uni = ui[0] * nh[0] + ui[1] * nh[1] + ui[2] * nh[2];
+  const double une = ue[0] * nh[0] + ue[1] * nh[1] + ue[2] * nh[2];
+  double rb, ub[3], pb;
+  if (uni >= ai) {  // supersonic outflow: everything from the interior
+    rb = ri;
+    pb = pi;
+    for (int a = 0; a < 3; ++a) ub[a] = ui[a];
+  } else if (uni <= -ai) {  // supersonic inflow: everything from the free stream
+    rb = re;
+    pb = pe;
+    for (int a = 0; a < 3; ++a) ub[a] = ue[a];
+  } else {
+    const double rp = uni + 2.0 * ai / (g - 1.0);
+    const double rm = une - 2.0 * ae / (g - 1.0);
+    const double unb = 0.5 * (rp + rm);
+    const double ab = 0.25 * (g - 1.0) * (rp - rm);
+    const bool out = unb > 0.0;
+    const double ent = out ? pi / std::pow(ri, g) : pe / std::pow(re, g);
+    const double* ut = out ? ui : ue;
+    const double unt = out ? uni : une;
+    for (int a = 0; a < 3; ++a) ub[a] = ut[a] + (unb - unt) * nh[a];
+    rb = std::pow(ab * ab / (g * ent), 1.0 / (g - 1.0));
+    pb = rb * ab * ab / g;
+  }
+  qb[0] = rb;
+  for (int a = 0; a < 3; ++a) qb[1 + a] = rb * ub[a];
+  qb[4] = pb / (g - 1.0) + 0.5 * rb * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+}
+
+// Boundary conditions on a state q after a stage (Sec. 3, boundary
+// conditions): for each bounded direction in the order xi, eta, zeta, every
+// node of its two boundary layers at each end is set from its face's rule --
+// supersonic inflow holds the value the node has in q0 (the state given at
+// the start of the step), far field applies farfield_state to the first
+// interior node along the direction (index 2, or n-3) with the face's
+// outward normal at the boundary node.  A node in the layers of an inflow
+// face is held at its inflow value whatever other faces it also belongs to;
+// otherwise a node in the boundary layers of several directions keeps the
+// value of the last of them.
+static void apply_bc(const Block& b, const jzo_params& P, const double* m, double* q, const double* q0) {
+  const long N = b.N;
+  for (int d = 0; d < 3; ++d) {
+    if (!b.bnd[d]) continue;
+    for (int k = 0; k < b.n[2]; ++k)
+      for (int j = 0; j < b.n[1]; ++j)
+        for (int i = 0; i < b.n[0]; ++i) {
+          int c[3] = {i, j, k};
+          const bool lo = c[d] < 2, hi = c[d] > b.n[d] - 3;
+          if (!lo && !hi) continue;
+          const long n = b.at(i, j, k);
+          bool held = false;  // in the layers of some inflow face
+          for (int e = 0; e < 3; ++e) {
+            if (!b.bnd[e]) continue;
+            if ((c[e] < 2 && P.bc[2 * e] == 1) || (c[e] > b.n[e] - 3 && P.bc[2 * e + 1] == 1)) held = true;
+          }
+          if (held) {
+            for (int v = 0; v < 5; ++v) q[v * N + n] = q0[v * N + n];
+            continue;
+          }
+          c[d] = lo ? 2 : b.n[d] - 3;
+          const long nr = b.at(c[0], c[1], c[2]);
+          double qi[5], qb[5], nh[3];
+          for (int v = 0; v < 5; ++v) qi[v] = q[v * N + nr];
+          // outward normal: -grad(xi_d) on the low face, +grad(xi_d) on the high face
+          const double J = m[9 * N + n];
+          double len = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            nh[a] = J * m[(3 * d + a) * N + n];
+            len += nh[a] * nh[a];
+          }
+          len = std::sqrt(len);
+          for (int a = 0; a < 3; ++a) nh[a] = (lo ? -nh[a] : nh[a]) / len;
+          farfield_state(P, qi, nh, qb);
+          for (int v = 0; v < 5; ++v) q[v * N + n] = qb[v];
+        }
+  }
+}
+
 static bool check(int ni, int nj, int nk, const jzo_params* p, const void* a, const void* b2) {
-  return ni >= 1 && nj >= 1 && nk >= 1 && p && a && b2 && p->n_stages >= 1 && p->n_stages <= 5;
+  if (!(ni >= 1 && nj >= 1 && nk >= 1 && p && a && b2 && p->n_stages >= 1 && p->n_stages <= 5)) return false;
+  const int n[3] = {ni, nj, nk};
+  for (int d = 0; d < 3; ++d) {
+    const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return false;
+    if ((lo == 0) != (hi == 0)) return false;   // periodic faces come in pairs
+    if (lo != 0 && n[d] < 5) return false;      // two boundary layers at each end
+  }
+  return true;
 }
 
 }  // namespace
@@ -401,7 +566,7 @@ extern "C" {
 int jzo_residual(int ni, int nj, int nk, const jzo_params* P, const double* m, const double* q,
                  double* r) {
   if (!check(ni, nj, nk, P, m, q) || !r) return -1;
-  Block b(ni, nj, nk);
+  Block b(ni, nj, nk, P->bc);
   Fields f(b.N);
   residual(b, *P, m, q, r, f);
   return 0;
@@ -412,7 +577,7 @@ int jzo_residual(int ni, int nj, int nk, const jzo_params* P, const double* m, c
 int jzo_fields(int ni, int nj, int nk, const jzo_params* P, const double* m, const double* q,
                double* mu, double* mut, double* lam, double* sig, double* nu, double* grad) {
   if (!check(ni, nj, nk, P, m, q)) return -1;
-  Block b(ni, nj, nk);
+  Block b(ni, nj, nk, P->bc);
   Fields f(b.N);
   node_fields(b, *P, m, q, f);
   const long N = b.N;
@@ -429,7 +594,7 @@ int jzo_fields(int ni, int nj, int nk, const jzo_params* P, const double* m, con
 int jzo_cfl_dt(int ni, int nj, int nk, const jzo_params* P, const double* m, const double* q,
                double* dt, double* lam_max) {
   if (!check(ni, nj, nk, P, m, q) || !dt) return -1;
-  Block b(ni, nj, nk);
+  Block b(ni, nj, nk, P->bc);
   const double mx = cfl_max(b, m, q, *P);
   if (lam_max) *lam_max = mx;
   *dt = (P->dt_fixed > 0.0) ? P->dt_fixed : P->cfl / mx;
@@ -443,7 +608,7 @@ int jzo_cfl_dt(int ni, int nj, int nk, const jzo_params* P, const double* m, con
 int jzo_step(int ni, int nj, int nk, const jzo_params* P, const double* m, double* q, double dt_in,
              double* dt_used, double* rms, double* linf) {
   if (!check(ni, nj, nk, P, m, q)) return -1;
-  Block b(ni, nj, nk);
+  Block b(ni, nj, nk, P->bc);
   const long N = b.N;
   double dt = dt_in;
   if (!(dt > 0.0)) {
@@ -454,8 +619,10 @@ int jzo_step(int ni, int nj, int nk, const jzo_params* P, const double* m, doubl
   std::vector<double> q0(q, q + 5 * N), qk(q, q + 5 * N), r(5 * N);
   Fields f(N);
   for (int s = 0; s < P->n_stages; ++s) {
-    residual(b, *P, m, qk.data(), r.data(), f);
+    residual(b, *P, m, qk.data(), r.data(), f);  // zero on boundary layers
     if (s == 0) {
+      // norms over the interior nodes (all nodes of a periodic block)
+      const double nint = (double)b.n_interior();
       for (int v = 0; v < 5; ++v) {
         double ss = 0.0, mx = 0.0;
         for (long n = 0; n < N; ++n) {
@@ -463,14 +630,24 @@ int jzo_step(int ni, int nj, int nk, const jzo_params* P, const double* m, doubl
           ss += x * x;
           mx = std::max(mx, std::fabs(x));
         }
-        if (rms) rms[v] = std::sqrt(ss / (double)N);
+        if (rms) rms[v] = std::sqrt(ss / nint);
         if (linf) linf[v] = mx;
       }
     }
     const double ad = P->rk_alpha[s] * dt;
     for (long n = 0; n < 5 * N; ++n) qk[n] = q0[n] - ad * r[n];
+    apply_bc(b, *P, m, qk.data(), q0.data());
   }
   std::memcpy(q, qk.data(), 5 * N * sizeof(double));
+  return 0;
+}
+
+// The boundary conditions alone, in place on q (5 x N): inflow layers take
+// their values from q0, far-field layers are recomputed from q.
+int jzo_apply_bc(int ni, int nj, int nk, const jzo_params* P, const double* m, double* q, const double* q0) {
+  if (!check(ni, nj, nk, P, m, q) || !q0) return -1;
+  Block b(ni, nj, nk, P->bc);
+  apply_bc(b, *P, m, q, q0);
   return 0;
 }
 

@@ -37,7 +37,12 @@ class Params(ctypes.Structure):
                 ("tv_alpha", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("dt_fixed", ctypes.c_double), ("rk_alpha", ctypes.c_double * 5),
                 ("n_stages", ctypes.c_int), ("precision", ctypes.c_int),
-                ("tile_i", ctypes.c_int), ("tile_j", ctypes.c_int), ("kchunk", ctypes.c_int)]
+                ("tile_i", ctypes.c_int), ("tile_j", ctypes.c_int), ("kchunk", ctypes.c_int),
+                ("bc", ctypes.c_int * 6), ("mach_inf", ctypes.c_double)]
+
+
+# face boundary types (jz_bc), indexed xi-, xi+, eta-, eta+, zeta-, zeta+
+JZ_BC_PERIODIC, JZ_BC_INFLOW, JZ_BC_FARFIELD = 0, 1, 2
 
 
 _lib = None
@@ -109,6 +114,11 @@ def params_default(**kw) -> Params:
         if k == "rk_alpha":
             for s in range(5):
                 p.rk_alpha[s] = v[s] if s < len(v) else 0.0
+        elif k == "bc":
+            if len(v) != 6:
+                raise ValueError("bc needs six face types")
+            for f in range(6):
+                p.bc[f] = int(v[f])
         elif hasattr(p, k):
             setattr(p, k, v)
         else:

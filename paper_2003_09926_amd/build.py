@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libjetles.so")
-SOURCES = ["jz_stage.hip", "jz_stage32.hip", "jz_batch.hip", "jz_aux.hip", "jz_api.hip"]
+SOURCES = ["jz_stage.hip", "jz_stage32.hip", "jz_bc.hip", "jz_aux.hip", "jz_api.hip"]
 ARCH = os.environ.get("JZ_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for every device pass.

@@ -28,7 +28,9 @@ hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk,
                                    int bx, int by, int grid_cap, int total, hipStream_t st);
 hipError_t launch_finalize_batch(const BlockDesc* desc, int nblk, hipStream_t st);
 hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst, long long N, hipStream_t st);
-hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, void* m, double* jac,
+hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
+                     const int n[3], const int bc[6], double gamma, double mach_inf, hipStream_t st);
+hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, int bnd, void* m, double* jac,
                              bool met32, hipStream_t st);
 hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int* flag, hipStream_t st);
 hipError_t launch_soa_to_met32(const double* src, float* m32, double* jac, long long N, hipStream_t st);
@@ -38,7 +40,7 @@ hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStre
 hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st);
 int lambda_max_blocks(long long N);
 hipError_t launch_lambda_max(const double* q, const void* met, const double* jac, bool met32, long long N,
-                             double gamma, double* part, hipStream_t st);
+                             const int n[3], Interior in, double gamma, double* part, hipStream_t st);
 hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCtl ctl, int* flag, hipStream_t st);
 hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
                                 int* flag, hipStream_t st);
@@ -83,6 +85,32 @@ struct Layout {
   long long np;
 };
 
+// bit d set when direction d has physical faces
+int bounded_mask(const jz_params* p) {
+  int m = 0;
+  for (int d = 0; d < 3; ++d)
+    if (p && p->bc[2 * d] != JZ_BC_PERIODIC) m |= 1 << d;
+  return m;
+}
+
+// the nodes the residual advances (all of a periodic direction; a bounded one
+// loses its two boundary layers at each end)
+Interior interior_of(int ni, int nj, int nk, const jz_params* p) {
+  Interior in;
+  const int n[3] = {ni, nj, nk};
+  in.bnd = bounded_mask(p);
+  for (int d = 0; d < 3; ++d) {
+    const bool b = (in.bnd >> d) & 1;
+    in.lo[d] = b ? 2 : 0;
+    in.hi[d] = b ? n[d] - 2 : n[d];
+  }
+  return in;
+}
+
+long long interior_count(const Interior& in) {
+  return (long long)(in.hi[0] - in.lo[0]) * (in.hi[1] - in.lo[1]) * (in.hi[2] - in.lo[2]);
+}
+
 void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   const bool f32 = p && p->precision == JZ_FP32_FLUX;
   // defaults measured on the 512 x 256 x 256 workload: FP64 28 x 12 tiles
@@ -96,12 +124,15 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   }
   t->ti = t->bx - 4;
   t->tj = t->by - 4;
-  t->tiles_i = (ni + t->ti - 1) / t->ti;
-  t->tiles_j = (nj + t->tj - 1) / t->tj;
+  // tiles and chunks cover the advanced nodes only
+  const Interior in = interior_of(ni, nj, nk, p);
+  const int ei = in.hi[0] - in.lo[0], ej = in.hi[1] - in.lo[1], ek = in.hi[2] - in.lo[2];
+  t->tiles_i = (ei + t->ti - 1) / t->ti;
+  t->tiles_j = (ej + t->tj - 1) / t->tj;
   int kc = (p && p->kchunk > 0) ? p->kchunk : 64;
-  if (kc > nk) kc = nk;
+  if (kc > ek) kc = ek;
   t->kchunk = kc;
-  t->nchunks = (nk + kc - 1) / kc;
+  t->nchunks = (ek + kc - 1) / kc;
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
 }
 
@@ -141,9 +172,11 @@ void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* 
   const int per_cu = (p && p->precision == JZ_FP32_FLUX) ? stage_wg_per_cu_fp32(t->bx, t->by)
                                                           : stage_wg_per_cu_fp64(t->bx, t->by);
   if (per_cu < 1 || ncu < 1) return;
-  const int kc = auto_kchunk(t->tiles_i * t->tiles_j, nk, (long long)per_cu * ncu);
+  const Interior in = interior_of(ni, nj, nk, p);
+  const int ek = in.hi[2] - in.lo[2];
+  const int kc = auto_kchunk(t->tiles_i * t->tiles_j, ek, (long long)per_cu * ncu);
   t->kchunk = kc;
-  t->nchunks = (nk + kc - 1) / kc;
+  t->nchunks = (ek + kc - 1) / kc;
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
 }
 
@@ -219,6 +252,32 @@ bool params_ok(const jz_params* p, std::string* why) {
     *why = "kchunk must be >= 0";
     return false;
   }
+  for (int d = 0; d < 3; ++d) {
+    const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
+    if (lo < JZ_BC_PERIODIC || lo > JZ_BC_FARFIELD || hi < JZ_BC_PERIODIC || hi > JZ_BC_FARFIELD) {
+      *why = "bc values must be JZ_BC_PERIODIC, JZ_BC_INFLOW or JZ_BC_FARFIELD";
+      return false;
+    }
+    if ((lo == JZ_BC_PERIODIC) != (hi == JZ_BC_PERIODIC)) {
+      *why = "a direction is periodic at both faces or at neither";
+      return false;
+    }
+  }
+  if (!std::isfinite(p->mach_inf)) {
+    *why = "mach_inf must be finite";
+    return false;
+  }
+  return true;
+}
+
+// sizes against the boundary layout: a bounded direction needs 5 nodes
+bool dims_ok(int ni, int nj, int nk, const jz_params* p, std::string* why) {
+  const int n[3] = {ni, nj, nk};
+  for (int d = 0; d < 3; ++d)
+    if ((bounded_mask(p) >> d & 1) && n[d] < 5) {
+      *why = "a direction with physical faces needs at least 5 nodes";
+      return false;
+    }
   return true;
 }
 
@@ -249,6 +308,7 @@ struct jz_solver {
   jz_params p;
   Phys ph;
   Tiling tl;
+  Interior in;      // nodes the residual advances
   int cap;          // tiles the partial-sum arrays can hold
   Layout L;
   hipStream_t stream;
@@ -312,7 +372,7 @@ size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
     jz_params_default(&d);
     p = &d;
   }
-  if (!params_ok(p, &why)) return 0;
+  if (!params_ok(p, &why) || !dims_ok(ni, nj, nk, p, &why)) return 0;
   Tiling t;
   pick_tiling(ni, nj, nk, p, &t);
   return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t)).total;
@@ -326,7 +386,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   if ((long long)ni * nj > (1LL << 30) || (long long)ni * nj * nk > (1LL << 36))
     return fail(JZ_EINVAL, "jz_create: block too large");
   std::string why;
-  if (!params_ok(p, &why)) return fail(JZ_EINVAL, "jz_create: %s", why.c_str());
+  if (!params_ok(p, &why) || !dims_ok(ni, nj, nk, p, &why)) return fail(JZ_EINVAL, "jz_create: %s", why.c_str());
   jz_solver* s = new jz_solver();
   s->ni = ni;
   s->nj = nj;
@@ -335,6 +395,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->p = *p;
   s->ph = make_phys(*p);
   pick_tiling_for_device(ni, nj, nk, p, &s->tl);
+  s->in = interior_of(ni, nj, nk, p);
   s->prec = p->precision;
   s->cap = partial_capacity(ni, nj, nk, s->tl);
   s->L = layout_for(s->N, s->tl, s->prec, s->cap);
@@ -439,7 +500,8 @@ int jz_set_grid_coords(jz_solver* s, const double* x, const double* y, const dou
   HIP_TRY(hipMemcpyAsync(X, x, bytes, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(X + s->N, y, bytes, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(X + 2 * s->N, z, bytes, hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(launch_metrics_tl(X, period, s->ni, s->nj, s->nk, s->met, s->jac, s->prec == JZ_FP32_FLUX, s->stream));
+  HIP_TRY(launch_metrics_tl(X, period, s->ni, s->nj, s->nk, s->in.bnd, s->met, s->jac, s->prec == JZ_FP32_FLUX,
+                            s->stream));
   return validate_metrics(s, "jz_set_grid_coords");
 }
 
@@ -513,6 +575,7 @@ static StageArgs stage_args(jz_solver* s, const void* qin, void* qout, double al
   a.tiles_j = s->tl.tiles_j;
   a.kchunk = s->tl.kchunk;
   a.nchunks = s->tl.nchunks;
+  a.in = s->in;
   a.ph = s->ph;
   return a;
 }
@@ -521,14 +584,15 @@ static StepCtl step_ctl(jz_solver* s) {
   StepCtl c;
   c.cfl = s->p.cfl;
   c.dt_fixed = s->p.dt_fixed;
-  c.inv_n = 1.0 / (double)s->N;
+  c.inv_n = 1.0 / (double)interior_count(s->in);
   return c;
 }
 
 static int ensure_dt(jz_solver* s) {
   if (s->dt_valid) return JZ_OK;
-  HIP_TRY(launch_lambda_max(s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, s->N, s->p.gamma, s->lam_part,
-                            s->stream));
+  const int n[3] = {s->ni, s->nj, s->nk};
+  HIP_TRY(launch_lambda_max(s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, s->N, n, s->in, s->p.gamma,
+                            s->lam_part, s->stream));
   HIP_TRY(launch_finalize_dt(s->clock, s->lam_part, lambda_max_blocks(s->N), step_ctl(s), s->flag, s->stream));
   s->dt_valid = true;
   return JZ_OK;
@@ -536,7 +600,7 @@ static int ensure_dt(jz_solver* s) {
 
 // algorithmic HBM bytes of one stage launch: every array read or written once
 static double stage_bytes(jz_solver* s, int stage) {
-  const double n = (double)s->N;
+  const double n = (double)interior_count(s->in);
   const int ns = s->p.n_stages;
   if (s->prec == JZ_FP64) {
     if (stage == 0) return n * (40.0 + 80.0 + 40.0);  // Q^n (which is also Q0), metrics, Q(1)
@@ -594,6 +658,11 @@ int jz_advance(jz_solver* s, int nsteps) {
         HIP_TRY(hipEventRecord(e0, s->stream));
       }
       HIP_TRY(launch_stage(s, a, k, ns, false));
+      if (s->in.bnd) {
+        const int n[3] = {s->ni, s->nj, s->nk};
+        HIP_TRY(launch_bc(out, s->prec == JZ_FP32_FLUX && !last, s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, n,
+                          s->p.bc, s->p.gamma, s->p.mach_inf, s->stream));
+      }
       if (s->timing) {
         HIP_TRY(hipEventRecord(e1, s->stream));
         s->ev.emplace_back(e0, e1);
@@ -667,6 +736,7 @@ int jz_eval_residual(jz_solver* s, double* r, int on_device) {
   if (!s || !r) return fail(JZ_EINVAL, "jz_eval_residual: NULL argument");
   if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_eval_residual: grid and state must be set first");
   StageArgs a = stage_args(s, s->q0, s->qa, 0.0);
+  if (s->in.bnd) HIP_TRY(hipMemsetAsync(s->qa, 0, 5 * s->N * sizeof(double), s->stream));  // boundary layers: R = 0
   HIP_TRY(launch_stage(s, a, 0, s->p.n_stages, true));
   HIP_TRY(launch_nodes_to_soa(s->qa, s->qb, s->N, 5, s->stream));
   HIP_TRY(hipMemcpyAsync(r, s->qb, 5 * s->N * sizeof(double),
@@ -824,6 +894,7 @@ int batch_upload(jz_batch* b) {
     D.kchunk = s->tl.kchunk;
     D.nchunks = s->tl.nchunks;
     D.ntiles = s->tl.nblocks;
+    D.in = s->in;
     D.ctl = step_ctl(s);
     D.ph = s->ph;
     off[i + 1] = off[i] + s->tl.nblocks;
@@ -885,6 +956,7 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
         return fail(JZ_EINVAL, "jz_batch_create: member %d has other stage coefficients", i);
     for (int j = 0; j < i; ++j)
       if (members[j] == s) return fail(JZ_EINVAL, "jz_batch_create: member %d repeated", i);
+    if (s->in.bnd) return fail(JZ_EINVAL, "jz_batch_create: member %d has physical boundaries (batches take periodic blocks)", i);
   }
   const bool shape_ok = f->prec == JZ_FP64 ? batch64_shape_supported(f->tl.bx, f->tl.by)
                                             : batch32_shape_supported(f->tl.bx, f->tl.by);

@@ -20,23 +20,36 @@ struct CoordView {
   const double* X;  // 3 x N coordinates
   long long N;
   int n[3];
+  int bnd;          // bit d: direction d bounded (no wrap; one-sided end differences)
   Period P;
-  // coordinate a of logical node (c0, c1, c2), unwrapped across the seams
-  __device__ double at(int a, int c0, int c1, int c2) const {
-    const long long idx = (long long)wrap_index(c0, n[0]) +
-                          (long long)n[0] * (wrap_index(c1, n[1]) + (long long)n[1] * wrap_index(c2, n[2]));
+  // coordinate a of logical node c, unwrapped across the periodic seams
+  __device__ double at(int a, const int c[3]) const {
+    const long long idx = (long long)wrap_index(c[0], n[0]) +
+                          (long long)n[0] * (wrap_index(c[1], n[1]) + (long long)n[1] * wrap_index(c[2], n[2]));
     double v = X[a * N + idx];
-    v += floor_div(c0, n[0]) * P.p[a];
-    v += floor_div(c1, n[1]) * P.p[3 + a];
-    v += floor_div(c2, n[2]) * P.p[6 + a];
+    v += floor_div(c[0], n[0]) * P.p[a];
+    v += floor_div(c[1], n[1]) * P.p[3 + a];
+    v += floor_div(c[2], n[2]) * P.p[6 + a];
     return v;
   }
-  // centred difference of coordinate a along direction d at logical node c
-  __device__ double dd(int a, int d, int c0, int c1, int c2) const {
-    int p[3] = {c0, c1, c2}, m[3] = {c0, c1, c2};
+  // difference of the node function g along d at logical node c: centred,
+  // or one-sided at the two end nodes of a bounded direction
+  template <class G>
+  __device__ double diff(const G& g, const int c[3], int d) const {
+    int p[3] = {c[0], c[1], c[2]}, m[3] = {c[0], c[1], c[2]};
+    if ((bnd >> d) & 1) {
+      if (c[d] == 0) {
+        p[d] += 1;
+        return g(p) - g(c);
+      }
+      if (c[d] == n[d] - 1) {
+        m[d] -= 1;
+        return g(c) - g(m);
+      }
+    }
     p[d] += 1;
     m[d] -= 1;
-    return 0.5 * (at(a, p[0], p[1], p[2]) - at(a, m[0], m[1], m[2]));
+    return 0.5 * (g(p) - g(m));
   }
 };
 
@@ -46,7 +59,10 @@ struct CoordView {
 // and (a, a1, a2),  S^d_a = delta_d2(X_a2 delta_d1 X_a1) - delta_d1(X_a2 delta_d2 X_a1),
 // with X_a2 measured from the centre node; J = 1 / det(delta_d X_a).  Because
 // the centred differences commute, sum_d delta_d S^d_a vanishes identically,
-// which keeps a uniform flow exactly steady on any grid.
+// which keeps a uniform flow exactly steady on any grid.  Along a bounded
+// direction the differences at its two end nodes are one-sided; they enter
+// only the metrics of the outermost boundary layer (the far-field normal),
+// never the residual of an advanced node.
 // MET32 = false: 10 doubles per node; true: 9 floats per node + J in double.
 template <bool MET32>
 __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, void* __restrict__ mout,
@@ -63,29 +79,23 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, void* __r
     const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
     for (int a = 0; a < 3; ++a) {
       const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
-      const double xc = cv.at(a2, i, j, k);
-      int p[3], q[3];
-      // delta_d2 ( X_a2 delta_d1 X_a1 )
-      for (int e = 0; e < 3; ++e) p[e] = q[e] = c[e];
-      p[d2] += 1;
-      q[d2] -= 1;
-      const double t1 = 0.5 * ((cv.at(a2, p[0], p[1], p[2]) - xc) * cv.dd(a1, d1, p[0], p[1], p[2]) -
-                               (cv.at(a2, q[0], q[1], q[2]) - xc) * cv.dd(a1, d1, q[0], q[1], q[2]));
-      // delta_d1 ( X_a2 delta_d2 X_a1 )
-      for (int e = 0; e < 3; ++e) p[e] = q[e] = c[e];
-      p[d1] += 1;
-      q[d1] -= 1;
-      const double t2 = 0.5 * ((cv.at(a2, p[0], p[1], p[2]) - xc) * cv.dd(a1, d2, p[0], p[1], p[2]) -
-                               (cv.at(a2, q[0], q[1], q[2]) - xc) * cv.dd(a1, d2, q[0], q[1], q[2]));
+      const double xc = cv.at(a2, c);
+      auto xa1 = [&](const int* e) { return cv.at(a1, e); };
+      // X_a2 delta_d1 X_a1 and X_a2 delta_d2 X_a1, X_a2 from the centre node
+      auto h1 = [&](const int* e) { return (cv.at(a2, e) - xc) * cv.diff(xa1, e, d1); };
+      auto h2 = [&](const int* e) { return (cv.at(a2, e) - xc) * cv.diff(xa1, e, d2); };
+      const double sda = cv.diff(h1, c, d2) - cv.diff(h2, c, d1);
       if (MET32)
-        m32[9 * n + 3 * d + a] = (float)(t1 - t2);
+        m32[9 * n + 3 * d + a] = (float)sda;
       else
-        m[10 * n + 3 * d + a] = t1 - t2;
+        m[10 * n + 3 * d + a] = sda;
     }
   }
   double M[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int d = 0; d < 3; ++d) M[a][d] = cv.dd(a, d, i, j, k);
+  for (int a = 0; a < 3; ++a) {
+    auto xa = [&](const int* e) { return cv.at(a, e); };
+    for (int d = 0; d < 3; ++d) M[a][d] = cv.diff(xa, c, d);
+  }
   const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
                      M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
                      M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
@@ -150,10 +160,15 @@ __global__ __launch_bounds__(256) void check_state_kernel(const double* __restri
 // dt of a restarted run is bitwise the dt of the uninterrupted one.
 template <bool MET32>
 __global__ __launch_bounds__(256) void lambda_max_kernel(const double* __restrict__ q, MetView<MET32> met,
-                                                         long long N, double gamma, double* __restrict__ part) {
+                                                         long long N, int ni, int nj, Interior in, double gamma,
+                                                         double* __restrict__ part) {
   __shared__ double red[256];
   double mx = 0.0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    if (in.bnd) {  // boundary layers are not advanced and do not set dt
+      const int i = (int)(n % ni), j = (int)((n / ni) % nj), k = (int)(n / ((long long)ni * nj));
+      if (i < in.lo[0] || i >= in.hi[0] || j < in.lo[1] || j >= in.hi[1] || k < in.lo[2] || k >= in.hi[2]) continue;
+    }
     double qq[5], mJ;
     typename std::conditional<MET32, float, double>::type mm[9];
     for (int c = 0; c < 5; ++c) qq[c] = q[5 * n + c];
@@ -288,15 +303,16 @@ __global__ __launch_bounds__(256) void nodes_to_soa_kernel(const double* __restr
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, void* m, double* jac,
-                             bool met32, hipStream_t st) {
+hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, int bnd, void* m,
+                             double* jac, bool met32, hipStream_t st) {
   CoordView cv;
   cv.X = X;
   cv.N = (long long)ni * nj * nk;
   cv.n[0] = ni;
   cv.n[1] = nj;
   cv.n[2] = nk;
-  for (int c = 0; c < 9; ++c) cv.P.p[c] = period9[c];
+  cv.bnd = bnd;
+  for (int c = 0; c < 9; ++c) cv.P.p[c] = ((bnd >> (c / 3)) & 1) ? 0.0 : period9[c];
   const long long nb = (cv.N + 255) / 256;
   if (met32)
     hipLaunchKernelGGL(metrics_tl_kernel<true>, dim3((unsigned)nb), dim3(256), 0, st, cv, m, jac);
@@ -343,17 +359,19 @@ hipError_t launch_nodes_to_soa(const double* src, double* dst, long long N, int 
 int lambda_max_blocks(long long N) { return (int)grid_stride_blocks(N); }
 
 hipError_t launch_lambda_max(const double* q, const void* met, const double* jac, bool met32, long long N,
-                             double gamma, double* part, hipStream_t st) {
+                             const int n[3], Interior in, double gamma, double* part, hipStream_t st) {
   if (met32) {
     MetView<true> mv;
     mv.m = (const float*)met;
     mv.jac = jac;
-    hipLaunchKernelGGL(lambda_max_kernel<true>, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, mv, N, gamma, part);
+    hipLaunchKernelGGL(lambda_max_kernel<true>, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, mv, N, n[0], n[1], in,
+                       gamma, part);
   } else {
     MetView<false> mv;
     mv.m = (const double*)met;
     mv.jac = jac;
-    hipLaunchKernelGGL(lambda_max_kernel<false>, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, mv, N, gamma, part);
+    hipLaunchKernelGGL(lambda_max_kernel<false>, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, mv, N, n[0], n[1], in,
+                       gamma, part);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,150 @@
+// jz_bc.hip -- physical boundary conditions of a block (Sec. 3, boundary
+// conditions): supersonic inflow at the jet exit (the state there is held)
+// and a far field computed from Riemann invariants.  They are applied to the
+// boundary layers of a stage output after the stage kernel has advanced the
+// interior, one launch per bounded direction in the order xi, eta, zeta.
+#include <type_traits>
+#include "jz_internal.h"
+
+namespace jz {
+
+namespace {
+
+struct BcArgs {
+  int n[3];
+  int d;                 // direction whose boundary layers this launch sets
+  int bc[6];             // face types (0 periodic, 1 inflow, 2 far field)
+  double gamma;
+  double mach_inf;       // free-stream velocity along x in ambient sound speeds
+  long long count;       // 4 layers x n_e x n_f nodes
+};
+
+// Far-field state from the one-dimensional characteristics normal to the face
+// (outward unit normal nh).  The outgoing invariant u_n + 2a/(gamma-1) is
+// taken from the interior state qi, the incoming u_n - 2a/(gamma-1) from the
+// free stream (rho = 1, u = (mach_inf, 0, 0), p = 1/gamma, a = 1); their sum
+// and difference give u_n and a at the face.  Entropy p/rho^gamma and the
+// tangential velocity come from the upwind side.  If the interior normal
+// velocity is supersonic, the upwind side supplies everything.
+__device__ void farfield_state(double g, double mach_inf, const double qi[5], const double nh[3], double qb[5]) {
+  const double ri = qi[0];
+  const double ui[3] = {qi[1] / ri, qi[2] / ri, qi[3] / ri};
+  const double pi = (g - 1.0) * (qi[4] - 0.5 * ri * (ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2]));
+  const double ai = sqrt(g * pi / ri);
+  const double re = 1.0, pe = 1.0 / g, ae = 1.0;
+  const double ue[3] = {mach_inf, 0.0, 0.0};
+  const double uni = ui[0] * nh[0] + ui[1] * nh[1] + ui[2] * nh[2];
+  const double une = ue[0] * nh[0] + ue[1] * nh[1] + ue[2] * nh[2];
+  double rb, pb, ub[3];
+  if (uni >= ai) {
+    rb = ri;
+    pb = pi;
+    for (int a = 0; a < 3; ++a) ub[a] = ui[a];
+  } else if (uni <= -ai) {
+    rb = re;
+    pb = pe;
+    for (int a = 0; a < 3; ++a) ub[a] = ue[a];
+  } else {
+    const double rp = uni + 2.0 * ai / (g - 1.0);
+    const double rm = une - 2.0 * ae / (g - 1.0);
+    const double unb = 0.5 * (rp + rm);
+    const double ab = 0.25 * (g - 1.0) * (rp - rm);
+    const bool out = unb > 0.0;
+    const double ent = out ? pi / pow(ri, g) : pe / pow(re, g);
+    const double* ut = out ? ui : ue;
+    const double unt = out ? uni : une;
+    for (int a = 0; a < 3; ++a) ub[a] = ut[a] + (unb - unt) * nh[a];
+    rb = pow(ab * ab / (g * ent), 1.0 / (g - 1.0));
+    pb = rb * ab * ab / g;
+  }
+  qb[0] = rb;
+  for (int a = 0; a < 3; ++a) qb[1 + a] = rb * ub[a];
+  qb[4] = pb / (g - 1.0) + 0.5 * rb * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+}
+
+// One thread per boundary-layer node of direction d.  Nodes read as
+// references (index 2 or n-3 along d) are never written by the same launch.
+template <typename T, bool MET32>
+__global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double* __restrict__ q0, MetView<MET32> met,
+                                                 BcArgs b) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b.count) return;
+  const int d = b.d, e = (d + 1) % 3, f = (d + 2) % 3;
+  const int layer = (int)(t % 4);
+  const long long r = t / 4;
+  int c[3];
+  c[d] = layer < 2 ? layer : b.n[d] - 4 + layer;  // 0, 1, n-2, n-1
+  c[e] = (int)(r % b.n[e]);
+  c[f] = (int)(r / b.n[e]);
+  const bool lo = layer < 2;
+  const long long node = c[0] + (long long)b.n[0] * (c[1] + (long long)b.n[1] * c[2]);
+  // supersonic inflow: a node in the layers of any inflow face is held at
+  // its Q(0) value, whichever other faces it belongs to
+  bool held = false;
+  for (int e = 0; e < 3; ++e) {
+    if (b.bc[2 * e] == 0) continue;
+    if ((c[e] < 2 && b.bc[2 * e] == 1) || (c[e] > b.n[e] - 3 && b.bc[2 * e + 1] == 1)) held = true;
+  }
+  if (held) {
+    if ((const void*)q != (const void*)q0) {
+      for (int v = 0; v < 5; ++v) q[5 * node + v] = (T)q0[5 * node + v];
+    }
+    return;
+  }
+  int cr[3] = {c[0], c[1], c[2]};
+  cr[d] = lo ? 2 : b.n[d] - 3;
+  const long long ref = cr[0] + (long long)b.n[0] * (cr[1] + (long long)b.n[1] * cr[2]);
+  double qi[5], qb[5], nh[3];
+  for (int v = 0; v < 5; ++v) qi[v] = (double)q[5 * ref + v];
+  typename std::conditional<MET32, float, double>::type sm[9];
+  double J;
+  met.load(node, sm, J);
+  double len = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    nh[a] = J * (double)sm[3 * d + a];  // grad xi_d
+    len += nh[a] * nh[a];
+  }
+  len = sqrt(len);
+  for (int a = 0; a < 3; ++a) nh[a] = (lo ? -nh[a] : nh[a]) / len;
+  farfield_state(b.gamma, b.mach_inf, qi, nh, qb);
+  for (int v = 0; v < 5; ++v) q[5 * node + v] = (T)qb[v];
+}
+
+template <typename T, bool MET32>
+hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double* jac, const int n[3],
+                           const int bc[6], double gamma, double mach_inf, hipStream_t st) {
+  MetView<MET32> mv;
+  mv.m = (decltype(mv.m))met;
+  mv.jac = jac;
+  for (int d = 0; d < 3; ++d) {
+    if (bc[2 * d] == 0) continue;
+    BcArgs b;
+    for (int e = 0; e < 3; ++e) b.n[e] = n[e];
+    b.d = d;
+    for (int f = 0; f < 6; ++f) b.bc[f] = bc[f];
+    b.gamma = gamma;
+    b.mach_inf = mach_inf;
+    b.count = 4LL * n[(d + 1) % 3] * n[(d + 2) % 3];
+    const long long blocks = (b.count + 255) / 256;
+    hipLaunchKernelGGL((bc_kernel<T, MET32>), dim3((unsigned)blocks), dim3(256), 0, st, q, q0, mv, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// Boundary conditions on the stage state q (node-major; double, or float when
+// q_float), with inflow layers taken from Q(0) = q0.  No-op for a periodic block.
+hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
+                     const int n[3], const int bc[6], double gamma, double mach_inf, hipStream_t st) {
+  if (q_float) {
+    if (met32) return launch_bc_typed<float, true>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
+    return launch_bc_typed<float, false>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
+  }
+  if (met32) return launch_bc_typed<double, true>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
+  return launch_bc_typed<double, false>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
+}
+
+}  // namespace jz

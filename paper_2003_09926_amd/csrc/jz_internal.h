@@ -41,6 +41,17 @@ struct StepCtl {
   double inv_n;       // 1 / N
 };
 
+// Nodes the residual advances: [lo[d], hi[d]) along each direction.  Bit d of
+// bnd is set when direction d ends in physical faces; then its two outermost
+// node layers at each end are boundary layers (lo = 2, hi = n - 2), set by
+// the boundary conditions, and stencil indices that would leave the block are
+// clamped to it instead of wrapped (only boundary-layer nodes, whose residual
+// is never used, reach that far).  A periodic direction has lo = 0, hi = n.
+struct Interior {
+  int lo[3], hi[3];
+  int bnd;
+};
+
 // Launch shape of the fused stage kernel.
 struct Tiling {
   int bx, by;         // workgroup = bx x by threads covering the tile and its 2-node halo
@@ -63,6 +74,7 @@ struct StageArgs {
   long long N;
   int ni, nj, nk;
   int tiles_i, tiles_j, kchunk, nchunks;
+  Interior in;          // tiles and chunks cover [lo, hi) of each direction
   Phys ph;
 };
 
@@ -82,6 +94,7 @@ struct BlockDesc {
   long long N;
   int ni, nj, nk;
   int tiles_i, tiles_j, kchunk, nchunks, ntiles;
+  Interior in;
   StepCtl ctl;
   Phys ph;
 };
@@ -89,6 +102,12 @@ struct BlockDesc {
 __host__ __device__ inline int wrap_index(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;
+}
+
+// index along a direction: periodic wrap, or clamped along a bounded one
+__host__ __device__ inline int map_index(int i, int n, bool bounded) {
+  if (!bounded) return wrap_index(i, n);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
 // NaN-propagating maximum (a plain fmax would drop a NaN).

@@ -29,9 +29,12 @@
 //     dissipation scales and pressure sensors of the same plane;
 //   * per march step s the lead plane s+2 is loaded, the gradient plane s+1
 //     gets its fluxes, and plane s gets its residual and is written.
-// Every global access uses periodically wrapped indices, so the halo is the
-// block's own periodic image (standing in for the neighbour-rank ghost
-// layers of Sec. 4.3).  Inside the library Q is stored node-major (the five
+// Along a periodic direction every global access uses wrapped indices, so
+// the halo is the block's own periodic image (standing in for the
+// neighbour-rank ghost layers of Sec. 4.3).  Along a direction with physical
+// faces the tiles cover only the interior nodes; the two boundary layers at
+// each end are read as halo (the boundary conditions set them after every
+// stage) and never written here.  Inside the library Q is stored node-major (the five
 // conserved variables of a node contiguous, 40 B) and the metric set likewise
 // (10 doubles, 80 B per node): one address per node and array, and a
 // wavefront still reads one contiguous span per plane row.
@@ -175,20 +178,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const int rest = lt / A.tiles_i;
   const int tile_j = rest % A.tiles_j;
   const int chunk = rest / A.tiles_j;
-  const int i0 = tile_i * TI, j0 = tile_j * TJ;
-  const int kbeg = chunk * A.kchunk;
-  const int kend = min(kbeg + A.kchunk, A.nk);
+  const int i0 = A.in.lo[0] + tile_i * TI, j0 = A.in.lo[1] + tile_j * TJ;
+  const int kbeg = A.in.lo[2] + chunk * A.kchunk;
+  const int kend = min(kbeg + A.kchunk, A.in.hi[2]);
 
   const int t = threadIdx.x;
   int tx, ty;
   const int role = tile_role<TI, TJ>(t, tx, ty);
   const int c = tx + BX * ty;                     // LDS slot of this column
   const int ui = i0 - 2 + tx, uj = j0 - 2 + ty;  // unwrapped column indices
-  const long long col = (long long)wrap_index(ui, A.ni) + (long long)A.ni * wrap_index(uj, A.nj);
+  const bool bi = A.in.bnd & 1, bj = A.in.bnd & 2, bk = A.in.bnd & 4;
+  const long long col = (long long)map_index(ui, A.ni, bi) + (long long)A.ni * map_index(uj, A.nj, bj);
   const long long plane = (long long)A.ni * A.nj;
   const bool isP = role <= 2;                     // supplies primitives and Q
   const bool isG = role <= 1;                     // computes fluxes
-  const bool isI = role == 0 && ui < A.ni && uj < A.nj;  // owns (writes) its column
+  const bool isI = role == 0 && ui < A.in.hi[0] && uj < A.in.hi[1];  // owns (writes) its column
 
   const TIn* __restrict__ qin = (const TIn*)A.qin;
   TOut* __restrict__ qout = (TOut*)A.qout;
@@ -199,7 +203,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const double adt = A.alpha * dt;
   const bool q0_is_input = (const void*)A.qin == (const void*)A.q0;
 
-  auto node = [&](int k) { return col + plane * wrap_index(k, A.nk); };
+  auto node = [&](int k) { return col + plane * map_index(k, A.nk, bk); };
   auto put_prims = [&](int slot, const Rl q[5]) {
     if (!isP) return;
     const Prim<Rl> p = primitives(q, gm1, gamma);
@@ -581,6 +585,7 @@ void stage_batch_kernel(const BlockDesc* __restrict__ desc,
     A.tiles_j = D.tiles_j;
     A.kchunk = D.kchunk;
     A.nchunks = D.nchunks;
+    A.in = D.in;
     A.ph = D.ph;
     __syncthreads();  // the previous tile's LDS readers are done
     stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, g - tile_off[a]);

@@ -119,6 +119,59 @@ def uniform_box(ni: int, nj: int, nk: int, lo=(0.0, -1.5, -1.5),
     return Grid(ni, nj, nk, X, Y, Z, period, m, name, axes=(xa, ya, za))
 
 
+# face boundary types, indexed xi-, xi+, eta-, eta+, zeta-, zeta+
+BC_PERIODIC, BC_INFLOW, BC_FARFIELD = 0, 1, 2
+# the jet domain: jet exit (supersonic inflow) at xi-, far field elsewhere
+JET_DOMAIN_BC = (BC_INFLOW, BC_FARFIELD, BC_FARFIELD, BC_FARFIELD, BC_FARFIELD, BC_FARFIELD)
+
+
+def bounded_box(ni: int, nj: int, nk: int, lo=(0.0, -1.5, -1.5), size=(4.0, 3.0, 3.0),
+                bounded=(True, True, True), name: str = "bounded") -> Grid:
+    """Uniform Cartesian block whose bounded directions carry nodes on both
+    end faces (spacing size / (n - 1)); periodic directions keep spacing
+    size / n and their period."""
+    n = (ni, nj, nk)
+    h = [size[d] / (n[d] - 1) if bounded[d] else size[d] / n[d] for d in range(3)]
+    ax = [lo[d] + np.arange(n[d], dtype=np.float64) * h[d] for d in range(3)]
+    X, Y, Z = _broadcast(*ax)
+    period = np.diag([0.0 if bounded[d] else size[d] for d in range(3)])
+    m = _separable_metrics(np.full(ni, h[0]), np.full(nj, h[1]), np.full(nk, h[2]))
+    return Grid(ni, nj, nk, X, Y, Z, period, m, name, axes=tuple(ax))
+
+
+def bounded_wavy_grid(ni: int, nj: int, nk: int, lo=(0.0, -1.5, -1.5), size=(4.0, 3.0, 3.0),
+                      amp=(0.1, 0.08, 0.06), bounded=(True, True, True), name: str = "bounded-wavy") -> Grid:
+    """Curvilinear block like ``wavy_grid`` whose bounded directions span
+    [lo, lo + size] with nodes on both ends (the wave phase 2 pi i / (n - 1)
+    there).  Coordinates only; ``jacobian`` holds the exact d x_a / d xi_d."""
+    n = (ni, nj, nk)
+    den = [n[d] - 1 if bounded[d] else n[d] for d in range(3)]
+    h = np.asarray(size, dtype=np.float64) / np.asarray(den, dtype=np.float64)
+    ii = np.arange(ni, dtype=np.float64)[None, None, :]
+    jj = np.arange(nj, dtype=np.float64)[None, :, None]
+    kk = np.arange(nk, dtype=np.float64)[:, None, None]
+    w = [2 * np.pi / den[d] for d in range(3)]
+    ti, tj, tk = w[0] * ii, w[1] * jj, w[2] * kk
+    ax, ay, az = amp
+    shp = (nk, nj, ni)
+    X = np.broadcast_to(lo[0] + h[0] * ii + ax * np.sin(tj) * np.sin(tk), shp).ravel().copy()
+    Y = np.broadcast_to(lo[1] + h[1] * jj + ay * np.sin(tk) * np.sin(ti), shp).ravel().copy()
+    Z = np.broadcast_to(lo[2] + h[2] * kk + az * np.sin(ti) * np.sin(tj), shp).ravel().copy()
+    jac = np.zeros((3, 3, ni * nj * nk))
+    bc = lambda a: np.broadcast_to(a, shp).ravel()
+    jac[0, 0] = h[0]
+    jac[0, 1] = bc(ax * w[1] * np.cos(tj) * np.sin(tk))
+    jac[0, 2] = bc(ax * np.sin(tj) * w[2] * np.cos(tk))
+    jac[1, 0] = bc(ay * np.sin(tk) * w[0] * np.cos(ti))
+    jac[1, 1] = h[1]
+    jac[1, 2] = bc(ay * w[2] * np.cos(tk) * np.sin(ti))
+    jac[2, 0] = bc(az * w[0] * np.cos(ti) * np.sin(tj))
+    jac[2, 1] = bc(az * np.sin(ti) * w[1] * np.cos(tj))
+    jac[2, 2] = h[2]
+    period = np.diag([0.0 if bounded[d] else size[d] for d in range(3)])
+    return Grid(ni, nj, nk, X, Y, Z, period, None, name, jacobian=jac)
+
+
 def _sech2_map(n: int, s0: float, s1: float, centres, amp: float, width: float):
     """Nodes of a periodic 1-D map whose point density is
     g(s) = 1 + amp * sum_c sech^2((s - c) / width) on [s0, s1).
@@ -317,6 +370,30 @@ def stretched_jet_case(dims=(512, 256, 256), mach: float = 1.4, seed: int = 2, s
     g = stretched_jet_grid(*dims, stride=stride)
     q = jet_state(g, mach, seed, global_dims=dims, stride=stride)
     return g, q
+
+
+def jet_domain_case(dims=(64, 48, 48), mach: float = 1.4, seed: int = 1, bc=JET_DOMAIN_BC,
+                    size=(4.0, 3.0, 3.0), noise_radius: Optional[float] = None):
+    """The jet in a bounded domain: x in [0, 4] from the jet exit, y, z in
+    [-1.5, 1.5], nodes on every bounded face.  The jet profile with seeded
+    noise fills the block (only within distance ``noise_radius`` of the axis
+    when given; the ambient fluid outside is then exactly at rest); the two
+    inflow layers at the jet exit (i = 0, 1) carry the clean profile.
+    Returns (grid, state, bc)."""
+    bounded = tuple(bc[2 * d] != BC_PERIODIC for d in range(3))
+    g = bounded_box(*dims, size=size, bounded=bounded)
+    q = jet_state(g, mach, seed)
+    clean = jet_state(g, mach, seed, noise=0.0)
+    if noise_radius is not None:
+        far = np.sqrt(g.y ** 2 + g.z ** 2) >= noise_radius
+        q[:, far] = clean[:, far]
+    q = q.reshape(5, dims[2], dims[1], dims[0])
+    clean = clean.reshape(5, dims[2], dims[1], dims[0])
+    if bc[0] == BC_INFLOW:
+        q[:, :, :, :2] = clean[:, :, :, :2]
+    if bc[1] == BC_INFLOW:
+        q[:, :, :, -2:] = clean[:, :, :, -2:]
+    return g, q.reshape(5, -1).copy(), tuple(bc)
 
 
 def batch_mix(seed: int = 4, nblocks: int = 64, lo: int = 32, hi: int = 160):

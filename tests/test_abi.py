@@ -46,6 +46,21 @@ def test_params_default_matches_oracle_defaults(lib):
         assert getattr(p, k) == getattr(o, k), k
     assert list(p.rk_alpha) == list(o.rk_alpha)
     assert p.precision == binding.JZ_FP64
+    assert list(p.bc) == list(o.bc) == [0] * 6 and p.mach_inf == o.mach_inf == 0.0
+
+
+def test_params_struct_sizes_match_the_libraries(lib):
+    """jz_params_default / jzo_params_default must write exactly the bytes of
+    the ctypes mirrors: a guard pattern after the struct stays untouched."""
+    for fill, size in ((lib.jz_params_default, ctypes.sizeof(binding.Params)),
+                       (oracle.core._load().jzo_params_default, ctypes.sizeof(oracle.Params))):
+        buf = (ctypes.c_ubyte * (size + 64))(*([0xAB] * (size + 64)))
+        saved, fill.argtypes = fill.argtypes, None
+        try:
+            assert fill(ctypes.cast(buf, ctypes.c_void_p)) == 0
+        finally:
+            fill.argtypes = saved
+        assert bytes(buf[size:]) == b"\xab" * 64
 
 
 def test_workspace_bytes_covers_state_and_metrics(lib):
@@ -70,6 +85,13 @@ def test_invalid_sizes_and_params_rejected_on_host(lib):
     assert lib.jz_create(8, 8, 8, ctypes.byref(bad), None, 0, None, ctypes.byref(h)) == binding.JZ_EINVAL
     bad = binding.params_default(gamma=1.0)
     assert binding.workspace_bytes((8, 8, 8), bad) == 0
+    bad = binding.params_default(bc=[1, 0, 0, 0, 0, 0])           # periodic faces come in pairs
+    assert binding.workspace_bytes((8, 8, 8), bad) == 0
+    bad = binding.params_default(bc=[1, 2, 0, 0, 0, 0])           # bounded direction with 4 nodes
+    assert binding.workspace_bytes((4, 8, 8), bad) == 0
+    assert binding.workspace_bytes((5, 8, 8), bad) > 0
+    bad = binding.params_default(bc=[3, 2, 0, 0, 0, 0])
+    assert lib.jz_create(8, 8, 8, ctypes.byref(bad), None, 0, None, ctypes.byref(h)) == binding.JZ_EINVAL
     assert lib.jz_advance(None, 1) == binding.JZ_EINVAL
 
 
