@@ -101,9 +101,12 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     """fp64 / fp32: the periodic stretched jet block.  domain-fp64 /
     domain-fp32: the jet in a bounded 512 x 256 x 256 domain (uniform grid
     over x in [0, 4], y, z in [-1.5, 1.5]) with supersonic inflow at the jet
-    exit and Riemann-invariant far field on the other five faces; the
-    boundary kernels run after every stage inside the timed region, and the
-    rate counts the advanced (interior) nodes."""
+    exit and Riemann-invariant far field on the other five faces.
+    cylinder-fp64 / cylinder-fp32: the jet on a 512 (axial) x 256 (radial) x
+    256 (azimuthal) cylindrical mesh, radius 1.5, with the jet exit, far field
+    at the outflow and lateral surface, the centreline and the periodic
+    azimuth.  In both, the boundary kernels run after every stage inside the
+    timed region, and the rate counts the advanced nodes."""
     import torch
     from paper_2003_09926_amd import binding as B
     from paper_2003_09926_amd import inputs as I
@@ -112,16 +115,24 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     prec_name = form.split("-")[-1]
     prec = B.JZ_FP64 if prec_name == "fp64" else B.JZ_FP32_FLUX
     domain = form.startswith("domain")
+    cylinder = form.startswith("cylinder")
     if domain:
         g, q, bc = I.jet_domain_case(DIMS, mach=1.4, seed=2)
         P = B.params_default(re_d=1.0e6, precision=prec, bc=bc)
         n_adv = (DIMS[0] - 4) * (DIMS[1] - 4) * (DIMS[2] - 4)
+    elif cylinder:
+        g, q, bc = I.jet_cylinder_case(DIMS, mach=1.4, seed=2)
+        P = B.params_default(re_d=1.0e6, precision=prec, bc=bc)
+        n_adv = (DIMS[0] - 4) * (DIMS[1] - 4) * DIMS[2]
     else:
         g, q = I.stretched_jet_case(DIMS, seed=2)
         P = B.params_default(re_d=1.0e6, precision=prec)
         n_adv = g.n
     s = B.Solver(g.dims, P)
-    s.set_grid_metrics(g.metrics)
+    if cylinder:
+        s.set_grid_coords(g.x, g.y, g.z, g.period)   # Thomas-Lombard metrics on the GPU
+    else:
+        s.set_grid_metrics(g.metrics)
     s.set_state(q)
     del q
     s.advance(warmup)
@@ -141,15 +152,16 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     bytes_per_launch = stage_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernel = "stage_fp64" if prec_name == "fp64" else "stage_fp32flux"
-    traffic = None if domain else _traffic(kernel)
+    traffic = None if (domain or cylinder) else _traffic(kernel)
     out = {
         "metric": "point-stage updates/s", "value": value, "unit": "point-stage updates/s",
         "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": el * 1e3 / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec_name == "fp64" else "f32 (fluxes) + f64 (accumulation, J, norms)",
         "data": "synthetic",
-        "config": {"workload": (f"jet_domain_512x256x256_inflow_farfield_{prec_name}" if domain
-                                else f"jet_512x256x256_stretched_{prec_name}"),
+        "config": {"workload": (f"jet_domain_512x256x256_inflow_farfield_{prec_name}" if domain else
+                                f"jet_cylinder_512x256x256_centreline_{prec_name}" if cylinder else
+                                f"jet_512x256x256_stretched_{prec_name}"),
                    "dims": list(DIMS), "mach": 1.4, "re_d": 1.0e6, "seed": 2, "stages_per_step": 5,
                    "form": form, "advanced_nodes": n_adv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -159,7 +171,7 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     }
     if with_error and form == "fp32":
         out["error_vs_oracle"] = fp32_error_vs_oracle()
-    if with_cpu and not domain:
+    if with_cpu and not (domain or cylinder):
         out["cpu_baseline"] = cpu_baseline()
     return out
 
@@ -272,10 +284,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", default="fp64",
-                    choices=["fp64", "fp32", "domain-fp64", "domain-fp32", "batch-fp64", "batch-fp32",
-                             "serve-fp64", "serve-fp32"],
+                    choices=["fp64", "fp32", "domain-fp64", "domain-fp32", "cylinder-fp64", "cylinder-fp32",
+                             "batch-fp64", "batch-fp32", "serve-fp64", "serve-fp32"],
                     help="fp64: FP64 path (default); fp32: FP32-flux form on the same workload; "
                          "domain-*: bounded jet domain with inflow and far-field faces; "
+                         "cylinder-*: cylindrical jet mesh with the centreline; "
                          "batch-*: 64 uneven blocks in one persistent launch per stage")
     ap.add_argument("--no-error", action="store_true", help="fp32 form: skip the error-vs-oracle run")
     ap.add_argument("--runs", type=int, default=100, help="serve forms: length of the arrival stream")

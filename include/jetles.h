@@ -68,12 +68,20 @@ typedef enum { JZ_FP64 = 0, JZ_FP32_FLUX = 1 } jz_precision;
  *                   u_n +- 2a/(gamma-1); entropy and tangential velocity come
  *                   from the upwind side; a supersonic normal flow takes all
  *                   values from its upwind side.  Both layers get that state.
+ *   JZ_BC_AXIS:     the centreline of a cylindrical mesh (eta- face only,
+ *                   zeta periodic: eta = radius index, j = 0 on the axis,
+ *                   zeta = azimuth): ring j = 1 takes the state of ring j = 2
+ *                   (extrapolation from the adjacent ring, per azimuth); every
+ *                   axis node j = 0 takes the average over all nk azimuths of
+ *                   ring j = 2, summed in the order k = 0..nk-1 (bitwise the
+ *                   same value for all k).  Axis nodes have no metrics (zero
+ *                   cell volume); they are never used and not validated.
  * A node in the layers of an inflow face is always held; otherwise the
  * bounded directions are processed in the order xi, eta, zeta, so a node in
  * the layers of several directions keeps the last one's value.  Residual
  * norms and the CFL maximum run over the advanced nodes only; jz_eval_residual
  * returns 0 on boundary layers.  Batches take periodic blocks only. */
-typedef enum { JZ_BC_PERIODIC = 0, JZ_BC_INFLOW = 1, JZ_BC_FARFIELD = 2 } jz_bc;
+typedef enum { JZ_BC_PERIODIC = 0, JZ_BC_INFLOW = 1, JZ_BC_FARFIELD = 2, JZ_BC_AXIS = 3 } jz_bc;
 
 /* Physical and numerical parameters.  Values the paper leaves open carry the
  * defaults of jz_params_default(); the paper fixes Pr = 0.72 (Sec. 3) and the
@@ -99,6 +107,9 @@ typedef struct {
   int bc[6];           /* jz_bc of the faces xi-, xi+, eta-, eta+, zeta-, zeta+ (all periodic) */
   double mach_inf;     /* free-stream velocity along x of the far field, in ambient
                           sound speeds (0) */
+  int stats_interval;  /* > 0: accumulate time-averaged statistics of the state after
+                          every stats_interval-th step of jz_advance (0: off; the
+                          workspace then holds no statistics) */
 } jz_params;
 
 /* Fill *p with the defaults listed above. */
@@ -180,6 +191,32 @@ int jz_eval_dt(jz_solver* s, double* dt, double* lambda_max);
  * those launches (each array read or written once per stage). */
 int jz_set_timing(jz_solver* s, int enable);
 int jz_get_timing(jz_solver* s, double* stage_ms, long long* stage_launches, double* stage_bytes);
+
+/* Time-averaged statistics (Sec. 6: the time average of the axial velocity
+ * <U> and the RMS of its fluctuation, from samples of the flow taken at a
+ * fixed frequency; here also the pressure).  With jz_params.stats_interval =
+ * m > 0 the library keeps, per node and in FP64, the sums of u, u^2, p and p^2
+ * (u = rho u / rho, the x component; p from the equation of state) over the
+ * samples, and jz_advance adds a sample of the new state after every m-th step
+ * counted from creation or the last jz_stats_reset.  Not available in batches.
+ * All four return JZ_ESTATE if statistics were not enabled. */
+int jz_stats_reset(jz_solver* s);   /* clears the sums and the step count */
+int jz_stats_sample(jz_solver* s);  /* adds a sample of the current state now */
+/* Per-node mean and RMS of the fluctuation, sqrt(max(<x^2> - <x>^2, 0)), of u
+ * and p (N doubles each; any pointer may be NULL; host arrays, or device
+ * pointers when on_device) and the sample count.  JZ_ESTATE without samples.
+ * Synchronises. */
+int jz_get_stats(jz_solver* s, double* mean_u, double* rms_u, double* mean_p, double* rms_p, long long* nsamples,
+                 int on_device);
+/* Azimuthal average over the cross-section xi = i (Sec. 6: radial profiles of
+ * the statistics averaged in the azimuthal direction).  bins (host, nj * nk
+ * ints, entry j + nj k for node (i, j, k)) assigns each node of the section
+ * to a bin 0..nbins-1 or -1 (not used); for every bin the node values of the
+ * four statistics are averaged over its nodes, visited in the fixed order
+ * k = 0.., j = 0.. (reproducible), and counts[b] is its node count.  Output
+ * host arrays of nbins entries (any may be NULL).  Synchronises. */
+int jz_stats_profile(jz_solver* s, int i, const int* bins, int nbins, double* mean_u, double* rms_u,
+                     double* mean_p, double* rms_p, long long* counts);
 
 /* Change the launch shape (tile_i x tile_j owned columns per workgroup, kchunk
  * planes marched per workgroup; 0 = default) of an existing solver.  Results

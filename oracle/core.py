@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
 
 
 # boundary types of the faces (xi-, xi+, eta-, eta+, zeta-, zeta+)
-BC_PERIODIC, BC_INFLOW, BC_FARFIELD = 0, 1, 2
+BC_PERIODIC, BC_INFLOW, BC_FARFIELD, BC_AXIS = 0, 1, 2, 3
 
 
 _lib = None

@@ -20,7 +20,9 @@
 //     every stage                                          Sec. 3; Sec. 4.2 and its flow chart
 //   * five-point dissipation stencil, two ghost layers     Sec. 4.3
 //   * physical boundaries: supersonic inflow at the jet
-//     exit, far field from Riemann invariants              Sec. 3, boundary conditions
+//     exit, far field from Riemann invariants, centreline
+//     of a cylindrical mesh (extrapolation + azimuthal
+//     average in a fixed order)                            Sec. 3, boundary conditions; Sec. 4.3
 // Points the paper leaves open (subgrid closure, dissipation constants, RK
 // coefficients, time-step rule, viscous stencil, metric form, scales) follow
 // the readings listed with the design notes; each is a field of jzo_params.
@@ -58,7 +60,9 @@ typedef struct {
   double rk_alpha[5];  // stage coefficients Q(k) = Q(0) - a_k dt R(Q(k-1))
   int n_stages;
   // boundary type of the faces xi-, xi+, eta-, eta+, zeta-, zeta+:
-  // 0 periodic, 1 supersonic inflow (state held), 2 far field (Riemann invariants)
+  // 0 periodic, 1 supersonic inflow (state held), 2 far field (Riemann
+  // invariants), 3 centreline (eta- only, zeta periodic: eta = radius from
+  // the axis, zeta = azimuth)
   int bc[6];
   double mach_inf;     // far-field stream velocity along x, in ambient sound speeds
 } jzo_params;
@@ -503,7 +507,12 @@ static void farfield_state(const jzo_params& P, const double qi[5], const double
 // supersonic inflow holds the value the node has in q0 (the state given at
 // the start of the step), far field applies farfield_state to the first
 // interior node along the direction (index 2, or n-3) with the face's
-// outward normal at the boundary node.  A node in the layers of an inflow
+// outward normal at the boundary node, and the centreline face of a
+// cylindrical mesh (eta = 0 is the axis) extrapolates the conserved variables
+// from the first advanced ring (j = 2) to the ring j = 1 and sets the axis
+// nodes j = 0 of every azimuth k to their average over k of that ring, summed
+// in the order k = 0, 1, ..., nk-1 (Sec. 3; the fixed order is the paper's
+// reproducibility rule of Sec. 4.3).  A node in the layers of an inflow
 // face is held at its inflow value whatever other faces it also belongs to;
 // otherwise a node in the boundary layers of several directions keeps the
 // value of the last of them.
@@ -525,6 +534,19 @@ static void apply_bc(const Block& b, const jzo_params& P, const double* m, doubl
           }
           if (held) {
             for (int v = 0; v < 5; ++v) q[v * N + n] = q0[v * N + n];
+            continue;
+          }
+          const int type = P.bc[2 * d + (hi ? 1 : 0)];
+          if (type == 3) {  // centreline
+            double acc[5] = {0, 0, 0, 0, 0};
+            if (c[1] == 1) {
+              for (int v = 0; v < 5; ++v) acc[v] = q[v * N + b.at(c[0], 2, c[2])];
+            } else {
+              for (int kk = 0; kk < b.n[2]; ++kk)
+                for (int v = 0; v < 5; ++v) acc[v] += q[v * N + b.at(c[0], 2, kk)];
+              for (int v = 0; v < 5; ++v) acc[v] /= (double)b.n[2];
+            }
+            for (int v = 0; v < 5; ++v) q[v * N + n] = acc[v];
             continue;
           }
           c[d] = lo ? 2 : b.n[d] - 3;
@@ -551,10 +573,13 @@ static bool check(int ni, int nj, int nk, const jzo_params* p, const void* a, co
   const int n[3] = {ni, nj, nk};
   for (int d = 0; d < 3; ++d) {
     const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return false;
+    if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return false;
     if ((lo == 0) != (hi == 0)) return false;   // periodic faces come in pairs
     if (lo != 0 && n[d] < 5) return false;      // two boundary layers at each end
   }
+  // the centreline is the eta- face of a mesh periodic in zeta (azimuth)
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] == 3 && (f != 2 || p->bc[4] != 0)) return false;
   return true;
 }
 

@@ -38,11 +38,11 @@ class Params(ctypes.Structure):
                 ("dt_fixed", ctypes.c_double), ("rk_alpha", ctypes.c_double * 5),
                 ("n_stages", ctypes.c_int), ("precision", ctypes.c_int),
                 ("tile_i", ctypes.c_int), ("tile_j", ctypes.c_int), ("kchunk", ctypes.c_int),
-                ("bc", ctypes.c_int * 6), ("mach_inf", ctypes.c_double)]
+                ("bc", ctypes.c_int * 6), ("mach_inf", ctypes.c_double), ("stats_interval", ctypes.c_int)]
 
 
 # face boundary types (jz_bc), indexed xi-, xi+, eta-, eta+, zeta-, zeta+
-JZ_BC_PERIODIC, JZ_BC_INFLOW, JZ_BC_FARFIELD = 0, 1, 2
+JZ_BC_PERIODIC, JZ_BC_INFLOW, JZ_BC_FARFIELD, JZ_BC_AXIS = 0, 1, 2, 3
 
 
 _lib = None
@@ -77,6 +77,10 @@ def library() -> ctypes.CDLL:
         "jz_eval_residual": ([S, dp, i], i),
         "jz_eval_dt": ([S, ctypes.POINTER(d), ctypes.POINTER(d)], i),
         "jz_set_timing": ([S, i], i),
+        "jz_stats_reset": ([S], i),
+        "jz_stats_sample": ([S], i),
+        "jz_get_stats": ([S, dp, dp, dp, dp, ctypes.POINTER(ll), i], i),
+        "jz_stats_profile": ([S, i, ctypes.c_void_p, i, dp, dp, dp, dp, ctypes.c_void_p], i),
         "jz_get_timing": ([S, ctypes.POINTER(d), ctypes.POINTER(ll), ctypes.POINTER(d)], i),
         "jz_destroy": ([S], i),
         "jz_set_tiling": ([S, i, i, i], i),
@@ -237,6 +241,34 @@ class Solver:
         dt, lm = ctypes.c_double(), ctypes.c_double()
         _check(library().jz_eval_dt(self._h, ctypes.byref(dt), ctypes.byref(lm)), "jz_eval_dt")
         return dt.value, lm.value
+
+    # -- statistics ---------------------------------------------------------
+    def stats_reset(self):
+        _check(library().jz_stats_reset(self._h), "jz_stats_reset")
+
+    def stats_sample(self):
+        _check(library().jz_stats_sample(self._h), "jz_stats_sample")
+
+    def stats(self) -> dict:
+        """per-node mean and RMS of the fluctuation of u and p, and the count"""
+        out = {k: np.empty(self.n) for k in ("mean_u", "rms_u", "mean_p", "rms_p")}
+        ns = ctypes.c_longlong()
+        _check(library().jz_get_stats(self._h, *[_host_ptr(out[k]) for k in ("mean_u", "rms_u", "mean_p", "rms_p")],
+                                      ctypes.byref(ns), 0), "jz_get_stats")
+        out["samples"] = ns.value
+        return out
+
+    def stats_profile(self, i: int, bins, nbins: int) -> dict:
+        """bin averages of the node statistics over the cross-section i"""
+        b = np.ascontiguousarray(bins, dtype=np.int32)
+        assert b.size == self.dims[1] * self.dims[2]
+        out = {k: np.empty(nbins) for k in ("mean_u", "rms_u", "mean_p", "rms_p")}
+        cnt = np.empty(nbins, dtype=np.int64)
+        _check(library().jz_stats_profile(self._h, int(i), b.ctypes.data, int(nbins),
+                                          *[_host_ptr(out[k]) for k in ("mean_u", "rms_u", "mean_p", "rms_p")],
+                                          cnt.ctypes.data), "jz_stats_profile")
+        out["count"] = cnt
+        return out
 
     # -- timing -------------------------------------------------------------
     def set_timing(self, enable: bool):

@@ -28,15 +28,20 @@ hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk,
                                    int bx, int by, int grid_cap, int total, hipStream_t st);
 hipError_t launch_finalize_batch(const BlockDesc* desc, int nblk, hipStream_t st);
 hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst, long long N, hipStream_t st);
+hipError_t launch_stats_accumulate(const double* q, double* acc, long long N, double gamma, hipStream_t st);
+hipError_t launch_stats_finalize(const double* acc, long long N, double inv_n, double* out, hipStream_t st);
+hipError_t launch_stats_profile(const double* soa, long long N, int ni, int nj, int nk, int i, const int* bins,
+                                int nbins, double* out, hipStream_t st);
 hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
                      const int n[3], const int bc[6], double gamma, double mach_inf, hipStream_t st);
 hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, int bnd, void* m, double* jac,
                              bool met32, hipStream_t st);
-hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int* flag, hipStream_t st);
+hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int axis_ni, int axis_nj, int* flag,
+                              hipStream_t st);
 hipError_t launch_soa_to_met32(const double* src, float* m32, double* jac, long long N, hipStream_t st);
 hipError_t launch_soa_to_nodes(const double* src, double* dst, long long N, int C, hipStream_t st);
 hipError_t launch_nodes_to_soa(const double* src, double* dst, long long N, int C, hipStream_t st);
-hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st);
+hipError_t launch_check_metrics(const double* m, long long N, int axis_ni, int axis_nj, int* flag, hipStream_t st);
 hipError_t launch_check_state(const double* q, long long N, double gm1, int* flag, hipStream_t st);
 int lambda_max_blocks(long long N);
 hipError_t launch_lambda_max(const double* q, const void* met, const double* jac, bool met32, long long N,
@@ -81,7 +86,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //              floats are the float stage states Q32a, Q32b) | metrics
 //              (9 floats per node) | J (1 double per node)
 struct Layout {
-  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, total;
+  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, stats, total;
   long long np;
 };
 
@@ -188,7 +193,7 @@ int partial_capacity(int ni, int nj, int nk, const Tiling& t) {
   return fine > t.nblocks ? fine : t.nblocks;
 }
 
-Layout layout_for(long long N, const Tiling& t, int prec, int cap) {
+Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats) {
   Layout L;
   std::memset(&L, 0, sizeof L);
   size_t off = 0;
@@ -213,6 +218,8 @@ Layout layout_for(long long N, const Tiling& t, int prec, int cap) {
   L.lam_part = take((size_t)lb * sizeof(double));
   L.clock = take(sizeof(Clock));
   L.flag = take(4 * sizeof(int));
+  // time-averaged statistics: sums of u, u^2, p, p^2 per node (node-major)
+  L.stats = stats ? take(4 * N * sizeof(double)) : 0;
   L.total = off;
   return L;
 }
@@ -252,10 +259,14 @@ bool params_ok(const jz_params* p, std::string* why) {
     *why = "kchunk must be >= 0";
     return false;
   }
+  if (p->stats_interval < 0) {
+    *why = "stats_interval must be >= 0";
+    return false;
+  }
   for (int d = 0; d < 3; ++d) {
     const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < JZ_BC_PERIODIC || lo > JZ_BC_FARFIELD || hi < JZ_BC_PERIODIC || hi > JZ_BC_FARFIELD) {
-      *why = "bc values must be JZ_BC_PERIODIC, JZ_BC_INFLOW or JZ_BC_FARFIELD";
+    if (lo < JZ_BC_PERIODIC || lo > JZ_BC_AXIS || hi < JZ_BC_PERIODIC || hi > JZ_BC_AXIS) {
+      *why = "bc values must be JZ_BC_PERIODIC, JZ_BC_INFLOW, JZ_BC_FARFIELD or JZ_BC_AXIS";
       return false;
     }
     if ((lo == JZ_BC_PERIODIC) != (hi == JZ_BC_PERIODIC)) {
@@ -263,6 +274,11 @@ bool params_ok(const jz_params* p, std::string* why) {
       return false;
     }
   }
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] == JZ_BC_AXIS && (f != 2 || p->bc[4] != JZ_BC_PERIODIC)) {
+      *why = "JZ_BC_AXIS is the eta- face of a mesh periodic in zeta";
+      return false;
+    }
   if (!std::isfinite(p->mach_inf)) {
     *why = "mach_inf must be finite";
     return false;
@@ -328,6 +344,9 @@ struct jz_solver {
   double* lam_part;
   Clock* clock;
   int* flag;
+  double* stats;          // sums of u, u^2, p, p^2 per node, or NULL
+  long long stat_samples; // samples in the sums
+  long long stat_steps;   // steps since the last reset (samples every stats_interval)
   // timing
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -375,7 +394,8 @@ size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
   if (!params_ok(p, &why) || !dims_ok(ni, nj, nk, p, &why)) return 0;
   Tiling t;
   pick_tiling(ni, nj, nk, p, &t);
-  return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t)).total;
+  return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t), p->stats_interval > 0)
+      .total;
 }
 
 int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
@@ -398,7 +418,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->in = interior_of(ni, nj, nk, p);
   s->prec = p->precision;
   s->cap = partial_capacity(ni, nj, nk, s->tl);
-  s->L = layout_for(s->N, s->tl, s->prec, s->cap);
+  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0);
   s->stream = (hipStream_t)hip_stream;
   s->timing = false;
   s->stage_ms_acc = 0;
@@ -441,12 +461,16 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->lam_part = (double*)(s->ws + s->L.lam_part);
   s->clock = (Clock*)(s->ws + s->L.clock);
   s->flag = (int*)(s->ws + s->L.flag);
+  s->stats = s->L.stats ? (double*)(s->ws + s->L.stats) : nullptr;
+  s->stat_samples = 0;
+  s->stat_steps = 0;
   s->grid_set = s->state_set = s->dt_valid = false;
   Clock c0;
   std::memset(&c0, 0, sizeof c0);
   int z[4] = {0, 0, 0, 0};
   e = hipMemcpyAsync(s->clock, &c0, sizeof c0, hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(s->flag, z, sizeof z, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess && s->stats) e = hipMemsetAsync(s->stats, 0, 4 * s->N * sizeof(double), s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
     if (s->owns_ws) (void)hipFree(s->ws);
@@ -473,10 +497,12 @@ static int clear_flag(jz_solver* s) {
 static int validate_metrics(jz_solver* s, const char* who) {
   int rc = clear_flag(s);
   if (rc) return rc;
+  // the centreline of a cylindrical mesh (j = 0) carries no metrics
+  const int axis_nj = s->p.bc[2] == JZ_BC_AXIS ? s->nj : 0;
   if (s->prec == JZ_FP64)
-    HIP_TRY(launch_check_metrics((const double*)s->met, s->N, s->flag, s->stream));
+    HIP_TRY(launch_check_metrics((const double*)s->met, s->N, s->ni, axis_nj, s->flag, s->stream));
   else
-    HIP_TRY(launch_check_met32((const float*)s->met, s->jac, s->N, s->flag, s->stream));
+    HIP_TRY(launch_check_met32((const float*)s->met, s->jac, s->N, s->ni, axis_nj, s->flag, s->stream));
   int f = 0;
   rc = read_flag(s, &f);
   if (rc) return rc;
@@ -672,6 +698,10 @@ int jz_advance(jz_solver* s, int nsteps) {
     }
     HIP_TRY(launch_finalize_step(s->clock, s->norm_part, s->lam_part, s->tl.nblocks, step_ctl(s), s->flag,
                                  s->stream));
+    if (s->stats && ++s->stat_steps % s->p.stats_interval == 0) {
+      HIP_TRY(launch_stats_accumulate(s->q0, s->stats, s->N, s->p.gamma, s->stream));
+      ++s->stat_samples;
+    }
   }
   return JZ_OK;
 }
@@ -756,6 +786,71 @@ int jz_eval_dt(jz_solver* s, double* dt, double* lambda_max) {
   *dt = c.dt;
   if (lambda_max) *lambda_max = c.lam_max;
   return rc;
+}
+
+int jz_stats_reset(jz_solver* s) {
+  if (!s) return fail(JZ_EINVAL, "jz_stats_reset: NULL solver");
+  if (!s->stats) return fail(JZ_ESTATE, "jz_stats_reset: statistics were not enabled (stats_interval = 0)");
+  HIP_TRY(hipMemsetAsync(s->stats, 0, 4 * s->N * sizeof(double), s->stream));
+  s->stat_samples = 0;
+  s->stat_steps = 0;
+  return JZ_OK;
+}
+
+int jz_stats_sample(jz_solver* s) {
+  if (!s) return fail(JZ_EINVAL, "jz_stats_sample: NULL solver");
+  if (!s->stats) return fail(JZ_ESTATE, "jz_stats_sample: statistics were not enabled (stats_interval = 0)");
+  if (!s->state_set) return fail(JZ_ESTATE, "jz_stats_sample: no state set");
+  HIP_TRY(launch_stats_accumulate(s->q0, s->stats, s->N, s->p.gamma, s->stream));
+  ++s->stat_samples;
+  return JZ_OK;
+}
+
+int jz_get_stats(jz_solver* s, double* mean_u, double* rms_u, double* mean_p, double* rms_p, long long* nsamples,
+                 int on_device) {
+  if (!s) return fail(JZ_EINVAL, "jz_get_stats: NULL solver");
+  if (!s->stats) return fail(JZ_ESTATE, "jz_get_stats: statistics were not enabled (stats_interval = 0)");
+  if (nsamples) *nsamples = s->stat_samples;
+  if (s->stat_samples == 0) return fail(JZ_ESTATE, "jz_get_stats: no samples yet");
+  HIP_TRY(launch_stats_finalize(s->stats, s->N, 1.0 / (double)s->stat_samples, s->qa, s->stream));
+  double* outs[4] = {mean_u, rms_u, mean_p, rms_p};
+  for (int f = 0; f < 4; ++f)
+    if (outs[f])
+      HIP_TRY(hipMemcpyAsync(outs[f], s->qa + f * s->N, s->N * sizeof(double),
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return JZ_OK;
+}
+
+int jz_stats_profile(jz_solver* s, int i, const int* bins, int nbins, double* mean_u, double* rms_u,
+                     double* mean_p, double* rms_p, long long* counts) {
+  if (!s || !bins) return fail(JZ_EINVAL, "jz_stats_profile: NULL argument");
+  if (i < 0 || i >= s->ni || nbins < 1) return fail(JZ_EINVAL, "jz_stats_profile: i or nbins out of range");
+  if (!s->stats) return fail(JZ_ESTATE, "jz_stats_profile: statistics were not enabled (stats_interval = 0)");
+  if (s->stat_samples == 0) return fail(JZ_ESTATE, "jz_stats_profile: no samples yet");
+  const long long plane = (long long)s->nj * s->nk;
+  for (long long t = 0; t < plane; ++t)
+    if (bins[t] < -1 || bins[t] >= nbins) return fail(JZ_EINVAL, "jz_stats_profile: bin index out of range");
+  if (4 * s->N + (long long)nbins * 5 + (plane + 1) / 2 + 1 > 10 * s->L.np)
+    return fail(JZ_EINVAL, "jz_stats_profile: too many bins for the scratch region");
+  // scratch: node statistics (4 x N), bin results (5 x nbins), bin indices
+  double* soa = s->qa;
+  double* res = soa + 4 * s->N;
+  int* dbins = (int*)(res + 5 * (long long)nbins);
+  HIP_TRY(launch_stats_finalize(s->stats, s->N, 1.0 / (double)s->stat_samples, soa, s->stream));
+  HIP_TRY(hipMemcpyAsync(dbins, bins, plane * sizeof(int), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(launch_stats_profile(soa, s->N, s->ni, s->nj, s->nk, i, dbins, nbins, res, s->stream));
+  std::vector<double> h(5 * (size_t)nbins);
+  HIP_TRY(hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int b = 0; b < nbins; ++b) {
+    if (mean_u) mean_u[b] = h[5 * b + 0];
+    if (rms_u) rms_u[b] = h[5 * b + 1];
+    if (mean_p) mean_p[b] = h[5 * b + 2];
+    if (rms_p) rms_p[b] = h[5 * b + 3];
+    if (counts) counts[b] = (long long)h[5 * b + 4];
+  }
+  return JZ_OK;
 }
 
 int jz_set_timing(jz_solver* s, int enable) {
@@ -957,6 +1052,7 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
     for (int j = 0; j < i; ++j)
       if (members[j] == s) return fail(JZ_EINVAL, "jz_batch_create: member %d repeated", i);
     if (s->in.bnd) return fail(JZ_EINVAL, "jz_batch_create: member %d has physical boundaries (batches take periodic blocks)", i);
+    if (s->stats) return fail(JZ_EINVAL, "jz_batch_create: member %d collects statistics (not sampled in batches)", i);
   }
   const bool shape_ok = f->prec == JZ_FP64 ? batch64_shape_supported(f->tl.bx, f->tl.by)
                                             : batch32_shape_supported(f->tl.bx, f->tl.by);

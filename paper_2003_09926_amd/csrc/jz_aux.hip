@@ -106,10 +106,18 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, void* __r
 }
 
 // flag |= 1 for a non-finite metric, |= 2 for J <= 0
-__global__ __launch_bounds__(256) void check_metrics_kernel(const double* __restrict__ m, long long N,
-                                                            int* __restrict__ flag) {
+// Nodes on the centreline of a cylindrical mesh (j = 0 when axis_nj > 0, with
+// axis_ni = ni, axis_nj = nj) have zero cell volume and no metrics; they are
+// never used (the centreline rule sets their state) and are not checked.
+__device__ inline bool on_axis(long long n, int axis_ni, int axis_nj) {
+  return axis_nj > 0 && (n / axis_ni) % axis_nj == 0;
+}
+
+__global__ __launch_bounds__(256) void check_metrics_kernel(const double* __restrict__ m, long long N, int axis_ni,
+                                                            int axis_nj, int* __restrict__ flag) {
   int bad = 0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    if (on_axis(n, axis_ni, axis_nj)) continue;
     for (int c = 0; c < 10; ++c)
       if (!isfinite(m[10 * n + c])) bad |= 1;
     if (!(m[10 * n + 9] > 0.0)) bad |= 2;
@@ -119,9 +127,11 @@ __global__ __launch_bounds__(256) void check_metrics_kernel(const double* __rest
 
 // same checks on the FP32-flux metric storage
 __global__ __launch_bounds__(256) void check_met32_kernel(const float* __restrict__ m32, const double* __restrict__ jac,
-                                                          long long N, int* __restrict__ flag) {
+                                                          long long N, int axis_ni, int axis_nj,
+                                                          int* __restrict__ flag) {
   int bad = 0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    if (on_axis(n, axis_ni, axis_nj)) continue;
     for (int c = 0; c < 9; ++c)
       if (!isfinite(m32[9 * n + c])) bad |= 1;
     if (!isfinite(jac[n])) bad |= 1;
@@ -326,13 +336,86 @@ static unsigned grid_stride_blocks(long long N) {
   return (unsigned)(nb < 2048 ? (nb < 1 ? 1 : nb) : 2048);
 }
 
-hipError_t launch_check_metrics(const double* m, long long N, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(check_metrics_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m, N, flag);
+hipError_t launch_check_metrics(const double* m, long long N, int axis_ni, int axis_nj, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(check_metrics_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m, N, axis_ni, axis_nj, flag);
   return hipGetLastError();
 }
 
-hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(check_met32_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m32, jac, N, flag);
+hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int axis_ni, int axis_nj, int* flag,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(check_met32_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, m32, jac, N, axis_ni, axis_nj,
+                     flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// time-averaged statistics (Sec. 6: mean axial velocity and the RMS of its
+// fluctuation, here also the pressure), accumulated in FP64 per node
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void stats_accumulate_kernel(const double* __restrict__ q, double* __restrict__ acc,
+                                                               long long N, double gamma) {
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    const double rho = q[5 * n], mx = q[5 * n + 1], my = q[5 * n + 2], mz = q[5 * n + 3], e = q[5 * n + 4];
+    const double u = mx / rho;
+    const double p = (gamma - 1.0) * (e - 0.5 * (mx * mx + my * my + mz * mz) / rho);
+    acc[4 * n + 0] += u;
+    acc[4 * n + 1] += u * u;
+    acc[4 * n + 2] += p;
+    acc[4 * n + 3] += p * p;
+  }
+}
+
+// sums -> mean and RMS of the fluctuation, sqrt(max(<x^2> - <x>^2, 0)),
+// structure of arrays: out[0..N) mean u, [N..2N) rms u, then mean p, rms p
+__global__ __launch_bounds__(256) void stats_finalize_kernel(const double* __restrict__ acc, long long N, double inv_n,
+                                                             double* __restrict__ out) {
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    const double mu = acc[4 * n] * inv_n, mp = acc[4 * n + 2] * inv_n;
+    const double vu = acc[4 * n + 1] * inv_n - mu * mu, vp = acc[4 * n + 3] * inv_n - mp * mp;
+    out[n] = mu;
+    out[N + n] = sqrt(vu > 0.0 ? vu : 0.0);
+    out[2 * N + n] = mp;
+    out[3 * N + n] = sqrt(vp > 0.0 ? vp : 0.0);
+  }
+}
+
+// Azimuthal (binned) average of the node statistics over the cross-section
+// i: one thread per bin visits the nodes of the plane in the fixed order
+// k = 0.., j = 0.. and averages those whose bin index matches, so the result
+// does not depend on scheduling.  out[5 b + 0..3] = averaged mean u, rms u,
+// mean p, rms p; out[5 b + 4] = node count.
+__global__ __launch_bounds__(64) void stats_profile_kernel(const double* __restrict__ soa, long long N, int ni, int nj,
+                                                           int nk, int i, const int* __restrict__ bins, int nbins,
+                                                           double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  double acc[4] = {0, 0, 0, 0};
+  long long cnt = 0;
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nj; ++j) {
+      if (bins[j + (long long)nj * k] != b) continue;
+      const long long n = i + (long long)ni * (j + (long long)nj * k);
+      for (int f = 0; f < 4; ++f) acc[f] += soa[f * N + n];
+      ++cnt;
+    }
+  for (int f = 0; f < 4; ++f) out[5 * b + f] = cnt ? acc[f] / (double)cnt : 0.0;
+  out[5 * b + 4] = (double)cnt;
+}
+
+hipError_t launch_stats_accumulate(const double* q, double* acc, long long N, double gamma, hipStream_t st) {
+  hipLaunchKernelGGL(stats_accumulate_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, q, acc, N, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_finalize(const double* acc, long long N, double inv_n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(stats_finalize_kernel, dim3(grid_stride_blocks(N)), dim3(256), 0, st, acc, N, inv_n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_profile(const double* soa, long long N, int ni, int nj, int nk, int i, const int* bins,
+                                int nbins, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(stats_profile_kernel, dim3((nbins + 63) / 64), dim3(64), 0, st, soa, N, ni, nj, nk, i, bins, nbins,
+                     out);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // jz_bc.hip -- physical boundary conditions of a block (Sec. 3, boundary
-// conditions): supersonic inflow at the jet exit (the state there is held)
-// and a far field computed from Riemann invariants.  They are applied to the
+// conditions): supersonic inflow at the jet exit (the state there is held),
+// a far field computed from Riemann invariants, and the centreline of a
+// cylindrical mesh (extrapolation from the adjacent ring and a fixed-order
+// azimuthal average, Sec. 3 and the reproducibility rule of Sec. 4.3).  They are applied to the
 // boundary layers of a stage output after the stage kernel has advanced the
 // interior, one launch per bounded direction in the order xi, eta, zeta.
 #include <type_traits>
@@ -13,7 +15,7 @@ namespace {
 struct BcArgs {
   int n[3];
   int d;                 // direction whose boundary layers this launch sets
-  int bc[6];             // face types (0 periodic, 1 inflow, 2 far field)
+  int bc[6];             // face types (0 periodic, 1 inflow, 2 far field, 3 centreline)
   double gamma;
   double mach_inf;       // free-stream velocity along x in ambient sound speeds
   long long count;       // 4 layers x n_e x n_f nodes
@@ -63,7 +65,8 @@ __device__ void farfield_state(double g, double mach_inf, const double qi[5], co
 }
 
 // One thread per boundary-layer node of direction d.  Nodes read as
-// references (index 2 or n-3 along d) are never written by the same launch.
+// references (index 2 or n-3 along d, all azimuths of ring 2 for the
+// centreline) are never written by the same launch.
 template <typename T, bool MET32>
 __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double* __restrict__ q0, MetView<MET32> met,
                                                  BcArgs b) {
@@ -89,6 +92,26 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
     if ((const void*)q != (const void*)q0) {
       for (int v = 0; v < 5; ++v) q[5 * node + v] = (T)q0[5 * node + v];
     }
+    return;
+  }
+  if ((lo ? b.bc[2 * d] : b.bc[2 * d + 1]) == 3) {
+    // centreline (eta- face, d = 1): ring j = 1 extrapolated from the first
+    // advanced ring j = 2 (zeroth order, per azimuth); axis nodes j = 0 set
+    // to the average over all azimuths of that ring, summed in the order
+    // k = 0, 1, ..., nk-1 by every thread alike (fixed order: every axis node
+    // of one i gets the bitwise same value)
+    double acc[5] = {0, 0, 0, 0, 0};
+    const long long row = (long long)b.n[0] * b.n[1];
+    if (c[1] == 1) {
+      const long long src = node + b.n[0];  // (i, 2, k)
+      for (int v = 0; v < 5; ++v) acc[v] = (double)q[5 * src + v];
+    } else {
+      const long long base = c[0] + 2LL * b.n[0];  // (i, 2, 0)
+      for (int kk = 0; kk < b.n[2]; ++kk)
+        for (int v = 0; v < 5; ++v) acc[v] += (double)q[5 * (base + kk * row) + v];
+      for (int v = 0; v < 5; ++v) acc[v] /= (double)b.n[2];
+    }
+    for (int v = 0; v < 5; ++v) q[5 * node + v] = (T)acc[v];
     return;
   }
   int cr[3] = {c[0], c[1], c[2]};

@@ -120,9 +120,12 @@ def uniform_box(ni: int, nj: int, nk: int, lo=(0.0, -1.5, -1.5),
 
 
 # face boundary types, indexed xi-, xi+, eta-, eta+, zeta-, zeta+
-BC_PERIODIC, BC_INFLOW, BC_FARFIELD = 0, 1, 2
+BC_PERIODIC, BC_INFLOW, BC_FARFIELD, BC_AXIS = 0, 1, 2, 3
 # the jet domain: jet exit (supersonic inflow) at xi-, far field elsewhere
 JET_DOMAIN_BC = (BC_INFLOW, BC_FARFIELD, BC_FARFIELD, BC_FARFIELD, BC_FARFIELD, BC_FARFIELD)
+# the cylindrical jet mesh: jet exit at xi-, far field at the outflow and the
+# lateral surface, the centreline at eta = 0, periodic azimuth
+JET_CYLINDER_BC = (BC_INFLOW, BC_FARFIELD, BC_AXIS, BC_FARFIELD, BC_PERIODIC, BC_PERIODIC)
 
 
 def bounded_box(ni: int, nj: int, nk: int, lo=(0.0, -1.5, -1.5), size=(4.0, 3.0, 3.0),
@@ -170,6 +173,38 @@ def bounded_wavy_grid(ni: int, nj: int, nk: int, lo=(0.0, -1.5, -1.5), size=(4.0
     jac[2, 2] = h[2]
     period = np.diag([0.0 if bounded[d] else size[d] for d in range(3)])
     return Grid(ni, nj, nk, X, Y, Z, period, None, name, jacobian=jac)
+
+
+def cylindrical_grid(ni: int, nj: int, nk: int, length: float = 4.0, radius: float = 1.5,
+                     name: str = "cylinder") -> Grid:
+    """Cylindrical mesh around the jet axis: xi axial (x = i length/(ni-1)),
+    eta radial (r = j radius/(nj-1), j = 0 on the centreline), zeta azimuthal
+    (theta = 2 pi k / nk, periodic with nk distinct points; the coordinates
+    repeat exactly, so the period shift is zero).  ``metrics`` holds the exact
+    metric set of the mapping: with h = (hx, hr, htheta) and
+    det = hx hr r htheta, S^xi = (hr r htheta, 0, 0),
+    S^eta = hx r htheta (0, cos, sin), S^zeta = hx hr (0, -sin, cos),
+    J = 1/det (infinite on the axis, where the cells have no volume)."""
+    hx, hr, ht = length / (ni - 1), radius / (nj - 1), 2.0 * np.pi / nk
+    x = np.arange(ni, dtype=np.float64) * hx
+    r = np.arange(nj, dtype=np.float64) * hr
+    th = np.arange(nk, dtype=np.float64) * ht
+    shp = (nk, nj, ni)
+    X = np.broadcast_to(x[None, None, :], shp).ravel().copy()
+    Y = np.broadcast_to(r[None, :, None] * np.cos(th)[:, None, None], shp).ravel().copy()
+    Z = np.broadcast_to(r[None, :, None] * np.sin(th)[:, None, None], shp).ravel().copy()
+    R = np.broadcast_to(r[None, :, None], shp).ravel()
+    C = np.broadcast_to(np.cos(th)[:, None, None], shp).ravel()
+    S = np.broadcast_to(np.sin(th)[:, None, None], shp).ravel()
+    m = np.zeros((10, ni * nj * nk))
+    m[0] = hr * R * ht
+    m[4] = hx * R * ht * C
+    m[5] = hx * R * ht * S
+    m[7] = -hx * hr * S
+    m[8] = hx * hr * C
+    with np.errstate(divide="ignore"):
+        m[9] = 1.0 / (hx * hr * R * ht)
+    return Grid(ni, nj, nk, X, Y, Z, np.zeros((3, 3)), m, name, axes=(x, r, th))
 
 
 def _sech2_map(n: int, s0: float, s1: float, centres, amp: float, width: float):
@@ -394,6 +429,23 @@ def jet_domain_case(dims=(64, 48, 48), mach: float = 1.4, seed: int = 1, bc=JET_
     if bc[1] == BC_INFLOW:
         q[:, :, :, -2:] = clean[:, :, :, -2:]
     return g, q.reshape(5, -1).copy(), tuple(bc)
+
+
+def jet_cylinder_case(dims=(40, 16, 24), mach: float = 1.4, seed: int = 1, noise_radius: Optional[float] = None,
+                      noise: float = 0.01):
+    """The jet on the cylindrical mesh (``cylindrical_grid``, jet axis on the
+    centreline) with ``JET_CYLINDER_BC``: jet profile plus seeded noise (within
+    ``noise_radius`` of the axis when given), the clean profile on the two
+    inflow layers.  Returns (grid, state, bc)."""
+    g = cylindrical_grid(*dims)
+    q = jet_state(g, mach, seed, noise=noise)
+    clean = jet_state(g, mach, seed, noise=0.0)
+    if noise_radius is not None:
+        far = np.sqrt(g.y ** 2 + g.z ** 2) >= noise_radius
+        q[:, far] = clean[:, far]
+    q = q.reshape(5, dims[2], dims[1], dims[0])
+    q[:, :, :, :2] = clean.reshape(5, dims[2], dims[1], dims[0])[:, :, :, :2]
+    return g, q.reshape(5, -1).copy(), JET_CYLINDER_BC
 
 
 def batch_mix(seed: int = 4, nblocks: int = 64, lo: int = 32, hi: int = 160):

@@ -193,3 +193,79 @@ def test_batch_rejects_bounded_members(B):
         with pytest.raises(B.JzError) as ei:
             B.Batch([s])
         assert ei.value.code == B.JZ_EINVAL
+
+
+def test_cylinder_centreline_parity(B):
+    """Cylindrical jet mesh (jet exit, far field, centreline, periodic
+    azimuth) with Thomas-Lombard metrics computed on both sides: metrics
+    (none on the axis), three steps per-step parity, axis nodes of one i
+    bitwise equal over the azimuth; one step with the exact metric set."""
+    _log("cylinder 40x16x24: metrics, three steps, exact-metric step")
+    dims = (40, 16, 24)
+    g, q, bc = I.jet_cylinder_case(dims, seed=7)
+    mo = oracle.metrics_tl(*dims, g.x, g.y, g.z, g.period, bc=bc)
+    P = oracle.default_params(bc=bc, re_d=2.0e4)
+    ni, nj, nk = dims
+    with B.Solver(dims, B.params_default(bc=bc, re_d=2.0e4)) as s:
+        s.set_grid_coords(g.x, g.y, g.z, g.period)
+        mg = s.get_grid_metrics()
+        fin = np.isfinite(mo[9])
+        assert np.array_equal(fin, np.isfinite(mg[9]))
+        assert not fin.reshape(nk, nj, ni)[:, 0, :].any() and fin.reshape(nk, nj, ni)[:, 1:, :].all()
+        scale = np.max(np.abs(mo[:9, fin]))
+        assert np.max(np.abs(mg[:9, fin] - mo[:9, fin])) <= 1e-13 * scale
+        assert np.max(np.abs(mg[9, fin] - mo[9, fin]) / mo[9, fin]) <= 1e-13
+        s.set_state(q)
+        qo = q.copy()
+        for step in range(3):
+            q_prev = qo
+            qo, _, rms_o, linf_o = oracle.step(dims, P, mo, qo)
+            s.advance(1)
+            qg = s.get_state()
+            rms, linf = s.residual_norms()
+            assert max(per_var_rel(qg, qo)) <= TOL_STATE, step
+            assert max(per_var_rel(qg - q_prev, qo - q_prev)) <= TOL_INC, step
+            assert np.allclose(rms, rms_o, rtol=1e-9, atol=0) and np.allclose(linf, linf_o, rtol=1e-9, atol=0)
+            axis = qg.reshape(5, nk, nj, ni)[:, :, 0, 2:]
+            assert np.all(axis == axis[:, :1, :])
+            s.set_state(qo)
+    qe, _, _, _ = oracle.step(dims, P, g.metrics, q)
+    with B.Solver(dims, B.params_default(bc=bc, re_d=2.0e4)) as s:
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        s.advance(1)
+        qg = s.get_state()
+    assert max(per_var_rel(qg, qe)) <= TOL_STATE
+    assert max(per_var_rel(qg - q, qe - q)) <= TOL_INC
+
+
+def test_cylinder_fp32_flux_form_close_to_oracle(B):
+    """FP32-flux form on the cylindrical mesh after 5 steps.  The transverse
+    momenta are small next to the axial one (noise only in the core), so the
+    momentum errors are measured against the whole momentum vector; density
+    and energy against their own norms."""
+    _log("cylinder 40x16x24 FP32-flux, 5 steps")
+    dims = (40, 16, 24)
+    g, q, bc = I.jet_cylinder_case(dims, seed=8, noise_radius=0.45)
+    P = oracle.default_params(bc=bc)
+    q5, _, _, _ = oracle.advance(dims, P, g.metrics, q, 5)
+    with B.Solver(dims, B.params_default(bc=bc, precision=B.JZ_FP32_FLUX)) as s:
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        s.advance(5)
+        g5 = s.get_state()
+    d = g5 - q5
+    mom = np.linalg.norm(q5[1:4])
+    errs = [np.linalg.norm(d[0]) / np.linalg.norm(q5[0])] + [np.linalg.norm(d[v]) / mom for v in (1, 2, 3)] + \
+        [np.linalg.norm(d[4]) / np.linalg.norm(q5[4])]
+    print("[gpu-case] fp32 cylinder errors", per_var_rel(g5, q5), errs, flush=True)
+    assert max(errs) <= 1e-5
+
+
+def test_axis_face_rules_are_validated(B):
+    _log("axis face validation")
+    for bad in ((FF, FF, FF, I.BC_AXIS, PER, PER), (I.BC_AXIS, FF, FF, FF, PER, PER),
+                (IN, FF, I.BC_AXIS, FF, FF, FF)):
+        with pytest.raises(B.JzError) as ei:
+            B.Solver((10, 8, 8), B.params_default(bc=bad))
+        assert ei.value.code == B.JZ_EINVAL

@@ -228,3 +228,87 @@ def test_far_field_lets_an_acoustic_pulse_leave():
     e_periodic = ((_prims(qp)[2] - 1 / G) ** 2).sum()
     assert e_periodic > 0.5 * e0
     assert e_left < 1e-6 * e0
+
+
+# --------------------------------------------------------------------------
+# centreline of a cylindrical mesh
+# --------------------------------------------------------------------------
+CYL = I.JET_CYLINDER_BC
+
+
+def _cyl(dims=(14, 9, 16), seed=5, noise=0.01):
+    g, q, bc = I.jet_cylinder_case(dims, seed=seed, noise=noise)
+    m = oracle.metrics_tl(*g.dims, g.x, g.y, g.z, g.period, bc=bc)
+    return g, q, bc, m
+
+
+def test_centreline_takes_the_ordered_azimuthal_mean_of_the_adjacent_ring():
+    import math
+    g, q, bc, m = _cyl()
+    ni, nj, nk = g.dims
+    rng = np.random.default_rng(3)
+    qr = q * (1.0 + 0.01 * rng.standard_normal(q.shape))
+    P = oracle.default_params(bc=bc)
+    qb = oracle.apply_bc(g.dims, P, m, qr, q).reshape(5, nk, nj, ni)
+    a = qr.reshape(5, nk, nj, ni)
+    for i in range(2, ni - 2):                     # inflow layers i < 2 are held
+        np.testing.assert_array_equal(qb[:, :, 1, i], a[:, :, 2, i])
+        axis = qb[:, :, 0, i]
+        assert np.all(axis == axis[:, :1])         # one value for every azimuth
+        for v in range(5):
+            assert axis[v, 0] == pytest.approx(math.fsum(a[v, :, 2, i]) / nk, rel=1e-15)
+    np.testing.assert_array_equal(qb[:, :, :, :2], q.reshape(5, nk, nj, ni)[:, :, :, :2])
+
+
+def test_uniform_stream_is_preserved_on_the_cylindrical_mesh():
+    g, _, bc, m = _cyl()
+    n = g.n
+    assert np.isinf(m[9].reshape(g.dims[2], g.dims[1], g.dims[0])[:, 0, :]).all()  # no metrics on the axis
+    q = I.conserved(np.ones(n), np.full(n, 0.5), np.zeros(n), np.zeros(n), np.full(n, 1 / G))
+    P = oracle.default_params(bc=bc, mach_inf=0.5, re_d=500.0)
+    q3, _, _, _ = oracle.advance(g.dims, P, m, q, 3)
+    np.testing.assert_allclose(q3, q, rtol=0, atol=1e-12)
+
+
+def _rotate_quarter(q, dims):
+    """the field turned by +90 degrees about the x axis on an nk = 4 m mesh:
+    node k takes the state of node k - nk/4 with (rho v, rho w) -> (-rho w, rho v)"""
+    ni, nj, nk = dims
+    a = q.reshape(5, nk, nj, ni)
+    b = np.roll(a, nk // 4, axis=1).copy()
+    v, w = b[2].copy(), b[3].copy()
+    b[2], b[3] = -w, v
+    return b.reshape(5, -1)
+
+
+def test_exact_cylindrical_metrics_match_thomas_lombard_off_the_axis():
+    """The metric set of the mapping and the discrete Thomas-Lombard set agree
+    to second order away from the axis and the one-sided end layers."""
+    errs = []
+    for n in (8, 16):
+        g = I.cylindrical_grid(4 * n, n + 1, 4 * n)
+        m = oracle.metrics_tl(*g.dims, g.x, g.y, g.z, g.period, bc=CYL)
+        ni, nj, nk = g.dims
+        sel = np.zeros((nk, nj, ni), bool)
+        sel[:, 2:-1, 1:-1] = True
+        sel = sel.ravel()
+        errs.append(np.abs(m[:9, sel] - g.metrics[:9, sel]).max() / np.abs(g.metrics[:9, sel]).max())
+    assert errs[1] < errs[0] / 3.0 and errs[1] < 1e-2
+
+
+def test_a_quarter_turn_commutes_with_the_step():
+    """With the exact metrics of the cylindrical mesh, the mesh and every
+    rule (far field, centreline average, inflow) are invariant under a turn
+    by a quarter of the azimuth, so stepping a turned state gives the turned
+    result (to the rounding of cos/sin).  (The Thomas-Lombard set is not
+    exactly invariant: its cyclic form treats the coordinates unequally.)"""
+    dims = (14, 9, 16)
+    g, q, bc, _ = _cyl(dims, seed=6)
+    m = g.metrics
+    P = oracle.default_params(bc=bc, re_d=3000.0)
+    qa, _, _, _ = oracle.advance(dims, P, m, q, 2)
+    qr = _rotate_quarter(q, dims)
+    qb, _, _, _ = oracle.advance(dims, P, m, qr, 2)
+    scale = np.abs(qa).max(axis=1, keepdims=True)
+    assert np.max(np.abs(qb - _rotate_quarter(qa, dims)) / scale) < 1e-12
+    assert np.max(np.abs(qa - q) / scale) > 1e-4          # the state did change
