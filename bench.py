@@ -97,7 +97,7 @@ def fp32_error_vs_oracle():
             "after_100_steps": dict(zip(names, rel(g100, o100)))}
 
 
-def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bool):
+def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bool, stats_interval: int = 0):
     """fp64 / fp32: the periodic stretched jet block.  domain-fp64 /
     domain-fp32: the jet in a bounded 512 x 256 x 256 domain (uniform grid
     over x in [0, 4], y, z in [-1.5, 1.5]) with supersonic inflow at the jet
@@ -122,7 +122,7 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
         n_adv = (DIMS[0] - 4) * (DIMS[1] - 4) * (DIMS[2] - 4)
     elif cylinder:
         g, q, bc = I.jet_cylinder_case(DIMS, mach=1.4, seed=2)
-        P = B.params_default(re_d=1.0e6, precision=prec, bc=bc)
+        P = B.params_default(re_d=1.0e6, precision=prec, bc=bc, stats_interval=stats_interval)
         n_adv = (DIMS[0] - 4) * (DIMS[1] - 4) * DIMS[2]
     else:
         g, q = I.stretched_jet_case(DIMS, seed=2)
@@ -146,6 +146,17 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     stage_ms, launches, stage_bytes = s.timing()
     s.set_timing(False)
     s.residual_norms()     # raises if the run went non-finite
+    stats_info = None
+    if cylinder and stats_interval > 0:
+        # the statistics of the run, and the potential core on the axis
+        # (ring j = 0; the jet exit velocity is the Mach number)
+        from paper_2003_09926_amd import stats as ST
+        st = s.stats()
+        ni, nj, nk = DIMS
+        axis_u = st["mean_u"].reshape(nk, nj, ni)[0, 0, :]
+        stats_info = {"interval": stats_interval, "samples": st["samples"],
+                      "potential_core_length": ST.potential_core_length(g.axes[0], axis_u, 1.4),
+                      "max_rms_u": float(st["rms_u"].max())}
     s.close()
     value = n_adv * 5 * steps / el
     avg_ms = stage_ms / max(launches, 1)
@@ -169,6 +180,8 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
                      "kernel": kernel, "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    if stats_info is not None:
+        out["stats"] = stats_info
     if with_error and form == "fp32":
         out["error_vs_oracle"] = fp32_error_vs_oracle()
     if with_cpu and not (domain or cylinder):
@@ -294,6 +307,8 @@ def main(argv=None):
     ap.add_argument("--runs", type=int, default=100, help="serve forms: length of the arrival stream")
     ap.add_argument("--no-sequential", action="store_true", help="serve forms: skip the alone baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--stats-interval", type=int, default=0,
+                    help="cylinder forms: accumulate time-averaged statistics every this many steps")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
@@ -319,7 +334,7 @@ def main(argv=None):
         out = run_serve(a.form.split("-")[1], a.runs, not a.no_sequential)
     else:
         out = run_block(a.form, a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu),
-                        with_error=not a.no_error)
+                        with_error=not a.no_error, stats_interval=a.stats_interval)
     if rank == 0:
         print(json.dumps(out), flush=True)
 
