@@ -256,7 +256,7 @@ def run_batch(prec_name: str, steps: int, warmup: int):
     }
 
 
-def run_serve(prec_name: str, nruns: int, with_sequential: bool):
+def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "streams"):
     """Config 5: Poisson arrivals (mean 20 runs/s, seed 5) of cubic jet runs
     n^3, n uniform in [48, 192], Mach U[1.2, 2.0], Re_D log-uniform
     [1e5, 1e6], 200 steps each at CFL 0.5, admitted under a 200 GB budget,
@@ -272,7 +272,8 @@ def run_serve(prec_name: str, nruns: int, with_sequential: bool):
     tile = (28, 12)
     stream = I.arrival_stream(seed=5, nruns=nruns, rate=20.0)
     runs = S.make_runs(stream)
-    srv = S.JetServer(precision=prec, budget_bytes=200 << 30, max_resident=32, chunk_steps=20, tile=tile)
+    srv = S.JetServer(precision=prec, budget_bytes=200 << 30, max_resident=32, chunk_steps=20, tile=tile,
+                      mode=mode)
     st = srv.serve(runs)
     summ = st.summary()
     out = {
@@ -283,7 +284,7 @@ def run_serve(prec_name: str, nruns: int, with_sequential: bool):
         "data": "synthetic",
         "config": {"workload": f"served_jet_runs_{prec_name}", "runs": nruns, "arrival_rate_per_s": 20.0,
                    "n_range": [48, 192], "steps_per_run": 200, "budget_gb": 200, "max_resident": 32,
-                   "chunk_steps": 20, "seed": 5, "form": f"serve-{prec_name}"},
+                   "chunk_steps": 20, "seed": 5, "form": f"serve-{prec_name}", "mode": mode},
         "serve": summ,
     }
     if with_sequential:
@@ -306,6 +307,8 @@ def main(argv=None):
     ap.add_argument("--no-error", action="store_true", help="fp32 form: skip the error-vs-oracle run")
     ap.add_argument("--runs", type=int, default=100, help="serve forms: length of the arrival stream")
     ap.add_argument("--no-sequential", action="store_true", help="serve forms: skip the alone baseline")
+    ap.add_argument("--serve-mode", default="streams", choices=["streams", "batch"],
+                    help="serve forms: resident runs on their own streams, or one batch over them")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--stats-interval", type=int, default=0,
                     help="cylinder forms: accumulate time-averaged statistics every this many steps")
@@ -331,7 +334,7 @@ def main(argv=None):
     if a.form.startswith("batch"):
         out = run_batch(a.form.split("-")[1], a.steps, a.warmup)
     elif a.form.startswith("serve"):
-        out = run_serve(a.form.split("-")[1], a.runs, not a.no_sequential)
+        out = run_serve(a.form.split("-")[1], a.runs, not a.no_sequential, a.serve_mode)
     else:
         out = run_block(a.form, a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu),
                         with_error=not a.no_error, stats_interval=a.stats_interval)

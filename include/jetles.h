@@ -224,6 +224,9 @@ int jz_stats_profile(jz_solver* s, int i, const int* bins, int nbins, double* me
  * JZ_EINVAL for an unsupported shape. */
 int jz_set_tiling(jz_solver* s, int tile_i, int tile_j, int kchunk);
 int jz_get_tiling(jz_solver* s, int* tile_i, int* tile_j, int* kchunk);
+/* Workgroups of the solver's stage kernel that one CU holds at once, and the
+ * device's CU count (their product is one round of workgroups). */
+int jz_get_occupancy(jz_solver* s, int* wg_per_cu, int* cus);
 
 /* Release the solver (and the workspace if the library allocated it). */
 int jz_destroy(jz_solver* s);

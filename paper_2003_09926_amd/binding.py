@@ -77,6 +77,7 @@ def library() -> ctypes.CDLL:
         "jz_eval_residual": ([S, dp, i], i),
         "jz_eval_dt": ([S, ctypes.POINTER(d), ctypes.POINTER(d)], i),
         "jz_set_timing": ([S, i], i),
+        "jz_get_occupancy": ([S, ctypes.POINTER(i), ctypes.POINTER(i)], i),
         "jz_stats_reset": ([S], i),
         "jz_stats_sample": ([S], i),
         "jz_get_stats": ([S, dp, dp, dp, dp, ctypes.POINTER(ll), i], i),
@@ -241,6 +242,12 @@ class Solver:
         dt, lm = ctypes.c_double(), ctypes.c_double()
         _check(library().jz_eval_dt(self._h, ctypes.byref(dt), ctypes.byref(lm)), "jz_eval_dt")
         return dt.value, lm.value
+
+    def occupancy(self):
+        """(stage workgroups per CU, CUs): their product is one round"""
+        w, c = ctypes.c_int(), ctypes.c_int()
+        _check(library().jz_get_occupancy(self._h, ctypes.byref(w), ctypes.byref(c)), "jz_get_occupancy")
+        return w.value, c.value
 
     # -- statistics ---------------------------------------------------------
     def stats_reset(self):

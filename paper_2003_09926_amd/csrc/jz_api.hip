@@ -906,6 +906,17 @@ int jz_set_tiling(jz_solver* s, int tile_i, int tile_j, int kchunk) {
   return JZ_OK;
 }
 
+int jz_get_occupancy(jz_solver* s, int* wg_per_cu, int* cus) {
+  if (!s) return fail(JZ_EINVAL, "jz_get_occupancy: NULL solver");
+  int ncu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device));
+  const int per = s->prec == JZ_FP32_FLUX ? stage_wg_per_cu_fp32(s->tl.bx, s->tl.by)
+                                           : stage_wg_per_cu_fp64(s->tl.bx, s->tl.by);
+  if (wg_per_cu) *wg_per_cu = per;
+  if (cus) *cus = ncu;
+  return JZ_OK;
+}
+
 int jz_get_tiling(jz_solver* s, int* tile_i, int* tile_j, int* kchunk) {
   if (!s) return fail(JZ_EINVAL, "jz_get_tiling: NULL solver");
   if (tile_i) *tile_i = s->tl.ti;

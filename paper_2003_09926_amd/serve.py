@@ -1,15 +1,26 @@
 """Served form: a request loop with continuous batching.
 
-Jet runs arrive over (wall-clock) time.  A run is admitted when it has
-arrived, a slot is free and its device footprint fits the HBM budget; its
-grid and initial state are then built directly in device memory and it joins
-the resident set.  The resident set advances together -- one batch (one
-persistent launch per RK stage, step replayed from a hipGraph) over all
-resident runs -- in chunks of steps no longer than the shortest remaining run,
-so runs that arrive while others are on the GPU join at the next chunk and
-finished runs leave, freeing their slot and memory.  Each run keeps its own
-state, metrics, clock and time step in HBM for its whole life.
+Jet runs arrive over (wall-clock) time and are served first come, first
+served.  A run is admitted when it has arrived, a slot is free, its device
+footprint fits the HBM budget, and the runs already resident do not yet give
+the stage kernel enough workgroups to fill the device (``fill_tiles``, one
+round of workgroups); its grid and initial state are then built directly in
+device memory and it joins the resident set.  Small runs thus share the GPU
+until together they fill it, while a run that fills it by itself runs alone
+and keeps first-come latency.  The resident set advances in chunks of steps no
+longer than the shortest remaining run, so runs that arrive while others are
+on the GPU join at the next chunk and finished runs leave, freeing their slot
+and memory.  Each run keeps its own state, metrics, clock and time step in
+HBM for its whole life.  Two ways of advancing the resident set:
 
+* ``mode="streams"`` (default): every run owns a HIP stream and the chunk of
+  each resident run is issued on it, so the device runs the stage kernels of
+  small runs side by side; joining and leaving cost nothing;
+* ``mode="batch"``: one batch over all resident runs (one persistent launch
+  per RK stage, step replayed from a hipGraph), rebuilt when the resident set
+  changes.
+
+The host never waits for a chunk, only for a run that completes.
 All GPU arithmetic happens in the HIP library through the C ABI; this module
 only schedules.
 """
@@ -40,6 +51,8 @@ class Run:
     remaining: int = 0
     footprint: int = 0
     solver: Optional[B.Solver] = None
+    tiles: int = 0
+    stream: object = None
     result: Optional[np.ndarray] = None
     ok: bool = True
 
@@ -62,18 +75,29 @@ def _params(run: Run, precision: int, tile):
                             tile_i=tile[0], tile_j=tile[1])
 
 
-def start_run(run: Run, precision: int, tile, device="cuda") -> B.Solver:
+def start_run(run: Run, precision: int, tile, device="cuda", stream=None) -> B.Solver:
     """Allocate the run's workspace, build its uniform jet box in device
-    memory and hand grid and state to the library."""
-    s = B.Solver(run.dims, _params(run, precision, tile))
-    m, q = I.jet_box_device(run.dims, run.mach, run.seed, device)
-    s.set_grid_metrics(m)
-    s.set_state(q.reshape(-1))
+    memory (on ``stream``, the run's own stream, when given) and hand grid and
+    state to the library."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(st):
+        s = B.Solver(run.dims, _params(run, precision, tile), stream=st)
+        m, q = I.jet_box_device(run.dims, run.mach, run.seed, device)
+        s.set_grid_metrics(m)
+        s.set_state(q.reshape(-1))
     return s
 
 
 def footprint(run: Run, precision: int, tile) -> int:
     return B.workspace_bytes(run.dims, _params(run, precision, tile))
+
+
+def stage_tiles(solver: B.Solver) -> int:
+    """workgroups of one stage launch of a (periodic) run"""
+    ti, tj, kc = solver.tiling()
+    ni, nj, nk = solver.dims
+    return -(-ni // ti) * -(-nj // tj) * -(-nk // kc)
 
 
 @dataclass
@@ -105,13 +129,20 @@ class JetServer:
     """Continuous-batching server for jet runs on one GPU."""
 
     def __init__(self, precision: int = B.JZ_FP64, budget_bytes: int = 200 << 30, max_resident: int = 64,
-                 chunk_steps: int = 20, tile=(28, 12), keep_results: bool = False):
+                 chunk_steps: int = 20, tile=(28, 12), keep_results: bool = False, fill_tiles: Optional[int] = None,
+                 mode: str = "streams"):
+        if mode not in ("streams", "batch"):
+            raise ValueError("mode is 'streams' or 'batch'")
+        self.mode = mode
         self.precision = precision
         self.budget = int(budget_bytes)
         self.max_resident = int(max_resident)
         self.chunk = int(chunk_steps)
         self.tile = tuple(tile)
         self.keep_results = keep_results
+        # workgroups that fill the device for one round of the stage kernel
+        # (None: taken from the first admitted run's occupancy)
+        self.fill_tiles = fill_tiles
 
     def serve(self, runs: List[Run], time_scale: float = 1.0) -> ServeStats:
         """Play the arrival stream (arrival times scaled by time_scale) and
@@ -120,7 +151,7 @@ class JetServer:
         pending = deque(sorted(runs, key=lambda r: r.arrival))
         resident: List[Run] = []
         batch: Optional[B.Batch] = None
-        used = 0
+        used, used_tiles = 0, 0
         max_res, max_bytes, chunks, failed = 0, 0, 0, 0
         point_stages = 0.0
         t0 = time.perf_counter()
@@ -129,6 +160,8 @@ class JetServer:
             changed = False
             # admission: arrived, a free slot, and the footprint fits the budget
             while pending and pending[0].arrival * time_scale <= now() and len(resident) < self.max_resident:
+                if resident and self.fill_tiles is not None and used_tiles >= self.fill_tiles:
+                    break                      # the resident runs already fill the device
                 r = pending[0]
                 fp = footprint(r, self.precision, self.tile)
                 if fp > self.budget:
@@ -140,10 +173,16 @@ class JetServer:
                     break
                 pending.popleft()
                 r.footprint = fp
-                r.solver = start_run(r, self.precision, self.tile)
+                r.stream = torch.cuda.Stream() if self.mode == "streams" else None
+                r.solver = start_run(r, self.precision, self.tile, stream=r.stream)
+                r.tiles = stage_tiles(r.solver)
+                if self.fill_tiles is None:
+                    per_cu, cus = r.solver.occupancy()
+                    self.fill_tiles = max(1, per_cu) * cus
                 r.admitted = now()
                 r.remaining = r.steps
                 used += fp
+                used_tiles += r.tiles
                 resident.append(r)
                 changed = True
             max_res = max(max_res, len(resident))
@@ -154,13 +193,24 @@ class JetServer:
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
-            if changed or batch is None:
+            # Enqueue the next chunk without waiting for the device: the host
+            # knows every run's progress, and the stream orders the work (a
+            # batch waits for earlier work on the stream and the stream for
+            # the batch).  The host waits only when a run completes.
+            n = min(self.chunk, min(r.remaining for r in resident))
+            if self.mode == "streams" or len(resident) == 1:
+                # each run's own launches, on its own stream
                 if batch is not None:
                     batch.close()
-                batch = B.Batch([r.solver for r in resident])
-            n = min(self.chunk, min(r.remaining for r in resident))
-            batch.advance(n)
-            batch.synchronize()
+                    batch = None
+                for r in resident:
+                    r.solver.advance(n)
+            else:
+                if changed or batch is None:
+                    if batch is not None:
+                        batch.close()
+                    batch = B.Batch([r.solver for r in resident])
+                batch.advance(n)
             chunks += 1
             point_stages += sum(r.points for r in resident) * 5.0 * n
             done = []
@@ -169,8 +219,14 @@ class JetServer:
                 if r.remaining == 0:
                     done.append(r)
             if done:
-                batch.close()
-                batch = None
+                if batch is not None:
+                    batch.close()
+                    batch = None
+                for r in done:
+                    if r.stream is not None:
+                        r.stream.synchronize()
+                    else:
+                        torch.cuda.synchronize()
                 t_done = now()
                 for r in done:
                     try:
@@ -185,6 +241,7 @@ class JetServer:
                     r.solver.close()
                     r.solver = None
                     used -= r.footprint
+                    used_tiles -= r.tiles
                     resident.remove(r)
         if batch is not None:
             batch.close()

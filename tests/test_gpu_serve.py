@@ -17,18 +17,19 @@ def _stream(n=10, steps=12):
                  steps=steps + 3 * (r % 3), seed=900 + r) for r in range(n)]
 
 
+@pytest.mark.parametrize("mode", ["streams", "batch"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_served_results_equal_alone_and_budget_holds(prec):
+def test_served_results_equal_alone_and_budget_holds(prec, mode):
     import torch
     assert torch.cuda.is_available()
     from paper_2003_09926_amd import binding as B, serve as S
-    print(f"[gpu-case] serve precision={prec}", flush=True)
+    print(f"[gpu-case] serve precision={prec} mode={mode}", flush=True)
     tile = (28, 12)
     runs = S.make_runs(_stream())
     big = max(S.footprint(r, prec, tile) for r in runs)
     budget = 3 * big
     srv = S.JetServer(precision=prec, budget_bytes=budget, max_resident=4, chunk_steps=5, tile=tile,
-                      keep_results=True)
+                      keep_results=True, mode=mode)
     st = srv.serve(runs)
     assert st.failed == 0 and st.runs == len(runs)
     assert st.max_resident > 1, "runs never overlapped"
