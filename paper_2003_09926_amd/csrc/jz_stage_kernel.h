@@ -92,6 +92,19 @@ __device__ inline float inv_cbrt(float J) {
   return r + r * (1.0f - J * r * r * r) * (1.0f / 3.0f);
 }
 
+// A register copy the compiler cannot fold into its source: the result gets
+// registers of its own (early clobber), distinct from the operand's.
+__device__ inline double move_apart(double x) {
+  double y;
+  asm volatile("v_mov_b64 %0, %1" : "=&v"(y) : "v"(x));
+  return y;
+}
+__device__ inline float move_apart(float x) {
+  float y;
+  asm volatile("v_mov_b32 %0, %1" : "=&v"(y) : "v"(x));
+  return y;
+}
+
 template <typename Rl>
 __device__ inline Rl sensor(Rl pm, Rl p0, Rl pp) {
   return div_pos(fabs(pp - Rl(2) * p0 + pm), pp + Rl(2) * p0 + pm);
@@ -143,6 +156,27 @@ __device__ inline int tile_role(int t, int& tx, int& ty) {
   return role;
 }
 
+// Row pitch (in slots) of the LDS plane buffers of a BX x BY workgroup.  With
+// a pitch of BX, the slots of one tile column lie BX elements apart and the
+// halo threads that walk a column hit the same LDS bank on every row; one
+// slot of padding per row spreads them over the banks.  The padding is taken
+// where the 39 plane buffers (slots up to the last one a thread uses: ring-2
+// corners have none; 32 bytes of alignment slack) still let the CU hold the
+// workgroups the register budget allows: two waves per SIMD in FP64, three in
+// the FP32-flux form.
+template <typename Rl, int BX, int BY>
+constexpr long long lds_plane_bytes(int pitch) {
+  return 39LL * ((BX - 2) + (long long)pitch * (BY - 1)) * (long long)sizeof(Rl) + 32;
+}
+template <typename Rl, int BX, int BY>
+constexpr int lds_pitch() {
+  constexpr long long kLds = 160 * 1024;
+  constexpr int waves = sizeof(Rl) == 4 ? 3 : 2;
+  constexpr long long want = (waves * 4 * 64 + BX * BY - 1) / (BX * BY);  // workgroups for that many waves
+  constexpr long long fit = kLds / lds_plane_bytes<Rl, BX, BY>(BX);
+  return kLds / lds_plane_bytes<Rl, BX, BY>(BX + 1) >= (want < fit ? want : fit) ? BX + 1 : BX;
+}
+
 }  // namespace
 
 // MODE bit 0: accumulate norms of R (first stage)
@@ -155,20 +189,23 @@ template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, 
 __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr int NT = BX * BY;
   constexpr int TI = BX - 4, TJ = BY - 4;
+  constexpr int P = lds_pitch<Rl, BX, BY>();   // LDS row pitch
+  constexpr int NS = (BX - 2) + P * (BY - 1);   // LDS slots per plane buffer
   constexpr bool NORMS = (MODE & 1) != 0;
   constexpr bool LAMMAX = (MODE & 2) != 0;
   constexpr bool WRITE_R = (MODE & 4) != 0;
   static_assert(TI * TJ + 4 * TI + 4 * TJ + 4 <= NT, "tile roles exceed the workgroup");
 
-  // plane buffers (structure of arrays, one slot per thread/column)
-  __shared__ Rl sPr[3][5][NT];     // ring of three planes of u, v, w, T, p
-  __shared__ Rl sQ2[2][5][NT];     // Q of the gradient plane, alternating between two buffers
-  __shared__ __attribute__((aligned(16))) Rl sF[10][NT];  // Fhat^xi (rows 0-4), Fhat^eta (rows 5-9)
-  Rl(*sFx)[NT] = sF;
-  Rl(*sFy)[NT] = sF + 5;
-  __shared__ Rl sSx[NT], sSy[NT];  // sigma^xi, sigma^eta
-  __shared__ Rl sNx[NT], sNy[NT];  // pressure sensor along xi, eta
+  // plane buffers (structure of arrays, one slot per tile column, rows of P)
+  __shared__ Rl sPr[3][5][NS];     // ring of three planes of u, v, w, T, p
+  __shared__ Rl sQ2[2][5][NS];     // Q of the gradient plane, alternating between two buffers
+  __shared__ __attribute__((aligned(16))) Rl sF[10][NS];  // Fhat^xi (rows 0-4), Fhat^eta (rows 5-9)
+  Rl(*sFx)[NS] = sF;
+  Rl(*sFy)[NS] = sF + 5;
+  __shared__ Rl sSx[NS], sSy[NS];  // sigma^xi, sigma^eta
+  __shared__ Rl sNx[NS], sNy[NS];  // pressure sensor along xi, eta
   // end-of-tile reductions reuse the flux buffer (free once the march is done)
+  static_assert(sizeof(Rl) * 10 * NS >= sizeof(double) * 2 * NT, "reduction rows exceed the flux buffer");
   double(*sRed)[NT] = reinterpret_cast<double(*)[NT]>(&sF[0][0]);
 
   const Phys ph = A.ph;
@@ -185,7 +222,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const int t = threadIdx.x;
   int tx, ty;
   const int role = tile_role<TI, TJ>(t, tx, ty);
-  const int c = tx + BX * ty;                     // LDS slot of this column
+  const int c = tx + P * ty;                      // LDS slot of this column
   const int ui = i0 - 2 + tx, uj = j0 - 2 + ty;  // unwrapped column indices
   const bool bi = A.in.bnd & 1, bj = A.in.bnd & 2, bk = A.in.bnd & 4;
   const long long col = (long long)map_index(ui, A.ni, bi) + (long long)A.ni * map_index(uj, A.nj, bj);
@@ -259,7 +296,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     // phase (before its second barrier), and Q goes to the other half of sQ2.
     // The flux, scale and sensor buffers are rewritten only after the next
     // barrier, which every thread reaches after finishing the owned phase.
-    Rl(*sQ)[NT] = sQ2[(s - kbeg) & 1];
+    Rl(*sQ)[NS] = sQ2[(s - kbeg) & 1];
     put_prims(slot_l, Ql);
     if (isP) {
 #pragma unroll
@@ -271,13 +308,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     Rl Fzg[5] = {0, 0, 0, 0, 0}, sigg = 0, nug = 0;
     double Jg = 0.0;
     if (isG) {
+      // Take the prefetched metrics out of the prefetch registers (into other
+      // registers: the early-clobber move keeps the two apart), so that the
+      // prefetch for the next plane can land in place and is waited for only
+      // where it is used, one march step later.
       Rl m[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) m[k] = Mn[k];
-      Jg = MJn;
+      for (int k = 0; k < 9; ++k) m[k] = move_apart(Mn[k]);
+      Jg = move_apart(MJn);
       if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
       const Rl J = (Rl)Jg;
-      const Rl(*Pg)[NT] = sPr[slot_g];
+      const Rl(*Pg)[NS] = sPr[slot_g];
+      // Every primitive this column needs from the three planes, read in one
+      // batch: the memory clobber keeps all the reads ahead of the arithmetic,
+      // so their latencies overlap instead of adding up.
+      Rl ctr[5], nxm[5], nxp[5], nym[5], nyp[5], nzm[5], nzp[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        ctr[q] = Pg[q][c];
+        nxm[q] = Pg[q][c - 1];
+        nxp[q] = Pg[q][c + 1];
+        nym[q] = Pg[q][c - P];
+        nyp[q] = Pg[q][c + P];
+        nzm[q] = sPr[slot_s][q][c];
+        nzp[q] = sPr[slot_l][q][c];
+      }
+      asm volatile("" ::: "memory");
       // chain rule d phi / d x_a = J sum_d S^d_a delta_d phi, with the 1/2 of
       // the centred difference folded into the metric factor
       Rl hm[9];
@@ -286,14 +342,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       Rl gr[4][3];  // gr[q][a] = d phi_q / d x_a for phi = u, v, w, T
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const Rl dxi = Pg[q][c + 1] - Pg[q][c - 1];
-        const Rl deta = Pg[q][c + BX] - Pg[q][c - BX];
-        const Rl dzeta = sPr[slot_l][q][c] - sPr[slot_s][q][c];
+        const Rl dxi = nxp[q] - nxm[q];
+        const Rl deta = nyp[q] - nym[q];
+        const Rl dzeta = nzp[q] - nzm[q];
 #pragma unroll
         for (int a = 0; a < 3; ++a) gr[q][a] = hm[a] * dxi + hm[3 + a] * deta + hm[6 + a] * dzeta;
       }
-      const Rl uu[3] = {Pg[0][c], Pg[1][c], Pg[2][c]};
-      const Rl T = Pg[3][c], p = Pg[4][c];
+      const Rl uu[3] = {ctr[0], ctr[1], ctr[2]};
+      const Rl T = ctr[3], p = ctr[4];
       const Rl asnd = sqrt_pos(T);
       const Rl mu = div_pos((Rl)ph.mu_suth * T * asnd, T + (Rl)ph.suth_s);
       // Smagorinsky: |S| = sqrt(2 S_ab S_ab), Delta = J^(-1/3)
@@ -358,9 +414,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       sSx[c] = sig[0];
       sSy[c] = sig[1];
       sigg = sig[2];
-      sNx[c] = sensor(Pg[4][c - 1], p, Pg[4][c + 1]);
-      sNy[c] = sensor(Pg[4][c - BX], p, Pg[4][c + BX]);
-      nug = sensor(sPr[slot_s][4][c], p, sPr[slot_l][4][c]);
+      sNx[c] = sensor(nxm[4], p, nxp[4]);
+      sNy[c] = sensor(nym[4], p, nyp[4]);
+      nug = sensor(nzm[4], p, nzp[4]);
     }
 
     // ---- owned columns, before the barrier: the zeta face between planes s
@@ -397,15 +453,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     if (own) {
       Rl Rg[5] = {0, 0, 0, 0, 0};
       {
-        // xi faces t-1/2 and t+1/2, eta faces t-BX/2 and t+BX/2
+        // xi faces c-1/2 and c+1/2, eta faces c-P/2 and c+P/2 (slots)
         const Rl e2xp = k2 * fmax(sNx[c], sNx[c + 1]);
         const Rl e2xm = k2 * fmax(sNx[c - 1], sNx[c]);
         const Rl e4xp = fmax(Rl(0), k4 - e2xp), e4xm = fmax(Rl(0), k4 - e2xm);
         const Rl sgxp = Rl(0.5) * (sSx[c] + sSx[c + 1]), sgxm = Rl(0.5) * (sSx[c - 1] + sSx[c]);
-        const Rl e2yp = k2 * fmax(sNy[c], sNy[c + BX]);
-        const Rl e2ym = k2 * fmax(sNy[c - BX], sNy[c]);
+        const Rl e2yp = k2 * fmax(sNy[c], sNy[c + P]);
+        const Rl e2ym = k2 * fmax(sNy[c - P], sNy[c]);
         const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
-        const Rl sgyp = Rl(0.5) * (sSy[c] + sSy[c + BX]), sgym = Rl(0.5) * (sSy[c - BX] + sSy[c]);
+        const Rl sgyp = Rl(0.5) * (sSy[c] + sSy[c + P]), sgym = Rl(0.5) * (sSy[c - P] + sSy[c]);
         // One variable per trip (not unrolled: the unrolled form runs out of
         // registers).  The results rotate through Rg so that no register is
         // indexed by the trip count.
@@ -414,21 +470,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
         for (int v = 0; v < 5; ++v) {
           // The empty asm hides the array base, so that every neighbour
           // access is one base register plus an immediate offset.
-          lds_ptr q = (lds_ptr)&sQ[v][c - 2 * BX];
+          lds_ptr q = (lds_ptr)&sQ[v][c - 2 * P];
           asm volatile("" : "+v"(q));
           lds_ptr fx = (lds_ptr)&sFx[v][c - 1];
           asm volatile("" : "+v"(fx));
-          lds_ptr fy = (lds_ptr)&sFy[v][c - BX];
+          lds_ptr fy = (lds_ptr)&sFy[v][c - P];
           asm volatile("" : "+v"(fy));
-          const Rl q0 = q[2 * BX];
-          const Rl qxp = q[2 * BX + 1], qxpp = q[2 * BX + 2], qxm = q[2 * BX - 1], qxmm = q[2 * BX - 2];
-          const Rl qyp = q[3 * BX], qypp = q[4 * BX], qym = q[BX], qymm = q[0];
+          const Rl q0 = q[2 * P];
+          const Rl qxp = q[2 * P + 1], qxpp = q[2 * P + 2], qxm = q[2 * P - 1], qxmm = q[2 * P - 2];
+          const Rl qyp = q[3 * P], qypp = q[4 * P], qym = q[P], qymm = q[0];
+          const Rl fxm = fx[0], fxp = fx[2], fym = fy[0], fyp = fy[2 * P];
+          asm volatile("" ::: "memory");  // all reads of the trip issued together
           const Rl dxp = sgxp * (e2xp * (qxp - q0) - e4xp * ((qxpp - qxm) - Rl(3) * (qxp - q0)));
           const Rl dxm = sgxm * (e2xm * (q0 - qxm) - e4xm * ((qxp - qxmm) - Rl(3) * (q0 - qxm)));
           const Rl dyp = sgyp * (e2yp * (qyp - q0) - e4yp * ((qypp - qym) - Rl(3) * (qyp - q0)));
           const Rl dym = sgym * (e2ym * (q0 - qym) - e4ym * ((qyp - qymm) - Rl(3) * (q0 - qym)));
-          const Rl cx = Rl(0.5) * (fx[2] - fx[0]);
-          const Rl cy = Rl(0.5) * (fy[2 * BX] - fy[0]);
+          const Rl cx = Rl(0.5) * (fxp - fxm);
+          const Rl cy = Rl(0.5) * (fyp - fym);
 #pragma unroll
           for (int r = 0; r < 4; ++r) Rg[r] = Rg[r + 1];
           Rg[4] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
