@@ -269,7 +269,7 @@ def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "st
 
     torch.cuda.set_device(0)
     prec = B.JZ_FP64 if prec_name == "fp64" else B.JZ_FP32_FLUX
-    tile = (28, 12)
+    tile = None  # the library's default tiling for the precision
     stream = I.arrival_stream(seed=5, nruns=nruns, rate=20.0)
     runs = S.make_runs(stream)
     srv = S.JetServer(precision=prec, budget_bytes=200 << 30, max_resident=32, chunk_steps=20, tile=tile,

@@ -118,11 +118,12 @@ long long interior_count(const Interior& in) {
 
 void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   const bool f32 = p && p->precision == JZ_FP32_FLUX;
-  // defaults measured on the 512 x 256 x 256 workload: FP64 28 x 12 tiles
-  // (one 512-thread workgroup per CU); FP32-flux 12 x 12 tiles (256 threads,
-  // up to three workgroups per CU)
-  t->bx = f32 ? 16 : 32;
-  t->by = f32 ? 16 : 16;
+  // defaults measured on the 512 x 256 x 256 workload: 32 owned columns per
+  // tile row (two 16-lane groups, so a row's LDS reads meet no bank conflict);
+  // FP64 32 x 8 tiles (four owned waves, one per SIMD; two waves per SIMD),
+  // FP32-flux 32 x 16 tiles (720 threads, three waves per SIMD)
+  t->bx = 36;
+  t->by = f32 ? 20 : 12;
   if (p && p->tile_i > 0 && p->tile_j > 0) {
     t->bx = p->tile_i + 4;
     t->by = p->tile_j + 4;
@@ -248,11 +249,11 @@ bool params_ok(const jz_params* p, std::string* why) {
     return false;
   }
   if (p->tile_i > 0 && p->precision == JZ_FP64 && !stage_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
-    *why = "unsupported FP64 tile shape (supported: 28x12, 60x4, 12x28, 28x4, 12x12)";
+    *why = "unsupported FP64 tile shape (supported: 28x12, 60x4, 12x28, 28x4, 12x12, 32x8, 16x16)";
     return false;
   }
   if (p->tile_i > 0 && p->precision == JZ_FP32_FLUX && !stage32_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
-    *why = "unsupported FP32-flux tile shape (supported: 28x12, 28x20, 12x12)";
+    *why = "unsupported FP32-flux tile shape (supported: 28x12, 28x20, 12x12, 32x16)";
     return false;
   }
   if (p->kchunk < 0) {
@@ -1250,9 +1251,9 @@ int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int*
   if (best_ti < 0) {
     std::vector<std::pair<int, int>> cand;
     if (b->prec == JZ_FP64)
-      cand = {{28, 12}, {12, 12}};
+      cand = {{32, 8}, {16, 16}, {28, 12}, {12, 12}};
     else
-      cand = {{28, 20}, {28, 12}, {12, 12}};
+      cand = {{32, 16}, {28, 20}, {12, 12}};
     const int kcs[3] = {16, 32, 64};
     // save states and clocks
     std::vector<double*> qsave(b->m.size(), nullptr);

@@ -28,7 +28,7 @@ static hipError_t launch_shape32(const StageArgs& a, const int* flag, int kind, 
 }
 
 bool stage32_shape_supported(int bx, int by) {
-  return (bx == 32 && by == 16) || (bx == 32 && by == 24) || (bx == 16 && by == 16);
+  return (bx == 32 && by == 16) || (bx == 32 && by == 24) || (bx == 16 && by == 16) || (bx == 36 && by == 20);
 }
 
 hipError_t launch_stage_fp32(const StageArgs& a, const int* flag, int kind, int bx, int by, int nblocks,
@@ -36,6 +36,7 @@ hipError_t launch_stage_fp32(const StageArgs& a, const int* flag, int kind, int 
   if (bx == 32 && by == 16) return launch_shape32<32, 16>(a, flag, kind, nblocks, st);
   if (bx == 32 && by == 24) return launch_shape32<32, 24>(a, flag, kind, nblocks, st);
   if (bx == 16 && by == 16) return launch_shape32<16, 16>(a, flag, kind, nblocks, st);
+  if (bx == 36 && by == 20) return launch_shape32<36, 20>(a, flag, kind, nblocks, st);
   return hipErrorInvalidValue;
 }
 
@@ -50,6 +51,8 @@ int stage_wg_per_cu_fp32(int bx, int by) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<float, float, float, true, 32, 24, 0>, 768, 0);
   else if (bx == 16 && by == 16)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<float, float, float, true, 16, 16, 0>, 256, 0);
+  else if (bx == 36 && by == 20)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<float, float, float, true, 36, 20, 0>, 720, 0);
   return e == hipSuccess ? per_cu : 0;
 }
 
@@ -83,7 +86,7 @@ static hipError_t batch_shape32(const BlockDesc* d, const int* off, int nblk, in
 }
 
 bool batch32_shape_supported(int bx, int by) {
-  return (bx == 32 && by == 24) || (bx == 32 && by == 16) || (bx == 16 && by == 16);
+  return (bx == 32 && by == 24) || (bx == 32 && by == 16) || (bx == 16 && by == 16) || (bx == 36 && by == 20);
 }
 
 hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
@@ -91,6 +94,7 @@ hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk,
   if (bx == 32 && by == 24) return batch_shape32<32, 24>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   if (bx == 32 && by == 16) return batch_shape32<32, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   if (bx == 16 && by == 16) return batch_shape32<16, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
+  if (bx == 36 && by == 20) return batch_shape32<36, 20>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   return hipErrorInvalidValue;
 }
 

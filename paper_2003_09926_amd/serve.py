@@ -71,8 +71,9 @@ def make_runs(stream: List[dict]) -> List[Run]:
 
 
 def _params(run: Run, precision: int, tile):
+    """Solver parameters of a run; tile None leaves the tiling to the library."""
     return B.params_default(precision=precision, mach_j=run.mach, re_d=run.re_d,
-                            tile_i=tile[0], tile_j=tile[1])
+                            tile_i=tile[0] if tile else 0, tile_j=tile[1] if tile else 0)
 
 
 def start_run(run: Run, precision: int, tile, device="cuda", stream=None) -> B.Solver:
@@ -129,7 +130,7 @@ class JetServer:
     """Continuous-batching server for jet runs on one GPU."""
 
     def __init__(self, precision: int = B.JZ_FP64, budget_bytes: int = 200 << 30, max_resident: int = 64,
-                 chunk_steps: int = 20, tile=(28, 12), keep_results: bool = False, fill_tiles: Optional[int] = None,
+                 chunk_steps: int = 20, tile=None, keep_results: bool = False, fill_tiles: Optional[int] = None,
                  mode: str = "streams"):
         if mode not in ("streams", "batch"):
             raise ValueError("mode is 'streams' or 'batch'")
@@ -138,7 +139,7 @@ class JetServer:
         self.budget = int(budget_bytes)
         self.max_resident = int(max_resident)
         self.chunk = int(chunk_steps)
-        self.tile = tuple(tile)
+        self.tile = tuple(tile) if tile else None
         self.keep_results = keep_results
         # workgroups that fill the device for one round of the stage kernel
         # (None: taken from the first admitted run's occupancy)

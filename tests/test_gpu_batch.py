@@ -40,7 +40,8 @@ def _members(B, cases, prec, tile, **extra):
     return ms
 
 
-@pytest.mark.parametrize("prec,tile", [(0, (28, 12)), (0, (12, 12)), (1, (28, 20)), (1, (12, 12))])
+@pytest.mark.parametrize("prec,tile", [(0, (28, 12)), (0, (12, 12)), (0, (32, 8)), (0, (16, 16)), (1, (28, 20)),
+                                       (1, (12, 12)), (1, (32, 16))])
 def test_batch_members_bitwise_equal_alone(B, prec, tile):
     print(f"[gpu-case] batch vs alone precision={prec} tile={tile}", flush=True)
     cases = _cases()

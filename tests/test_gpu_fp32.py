@@ -90,7 +90,8 @@ def test_result_independent_of_launch_shape(B, prec):
     through the partial-sum order)."""
     print(f"[gpu-case] launch-shape independence precision={prec}", flush=True)
     g, q = I.jet_box_case((37, 23, 19), seed=11)
-    shapes = [(28, 12, 0), (12, 12, 5)] + ([(28, 20, 3)] if prec == 1 else [(60, 4, 3), (12, 28, 1)])
+    shapes = [(28, 12, 0), (12, 12, 5)] + ([(28, 20, 3), (32, 16, 0), (32, 16, 4)] if prec == 1 else
+                                           [(60, 4, 3), (12, 28, 1), (32, 8, 0), (16, 16, 3)])
     ref = None
     for ti, tj, kc in shapes:
         s = B.Solver(g.dims, B.params_default(precision=prec, tile_i=ti, tile_j=tj, kchunk=kc))

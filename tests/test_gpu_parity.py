@@ -131,7 +131,8 @@ def test_multi_step_drift_stays_at_roundoff(B):
 
 
 @pytest.mark.parametrize("tile,kchunk", [((28, 12), 0), ((60, 4), 3), ((12, 28), 1), ((28, 4), 5),
-                                         ((12, 12), 7), ((28, 12), 19)])
+                                         ((12, 12), 7), ((28, 12), 19), ((32, 8), 0), ((32, 8), 4),
+                                         ((16, 16), 6)])
 def test_launch_shapes_agree(B, tile, kchunk):
     _log(f"launch shape tile={tile} kchunk={kchunk} on 37x23x19")
     g, q = I.jet_box_case((37, 23, 19), seed=6)
