@@ -105,10 +105,6 @@ __device__ inline float move_apart(float x) {
   return y;
 }
 
-template <typename Rl>
-__device__ inline Rl sensor(Rl pm, Rl p0, Rl pp) {
-  return div_pos(fabs(pp - Rl(2) * p0 + pm), pp + Rl(2) * p0 + pm);
-}
 
 
 // Role of thread t in a TI x TJ tile with a two-node halo: position (tx, ty)
@@ -414,9 +410,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       sSx[c] = sig[0];
       sSy[c] = sig[1];
       sigg = sig[2];
-      sNx[c] = sensor(nxm[4], p, nxp[4]);
-      sNy[c] = sensor(nym[4], p, nyp[4]);
-      nug = sensor(nzm[4], p, nzp[4]);
+      // pressure sensors |p+ - 2p + p-| / (p+ + 2p + p-) along xi, eta, zeta,
+      // the three divisions through one reciprocal of the product of the
+      // (positive) denominators
+      {
+        const Rl ax = fabs(nxp[4] - Rl(2) * p + nxm[4]), bx = nxp[4] + Rl(2) * p + nxm[4];
+        const Rl ay = fabs(nyp[4] - Rl(2) * p + nym[4]), by = nyp[4] + Rl(2) * p + nym[4];
+        const Rl az = fabs(nzp[4] - Rl(2) * p + nzm[4]), bz = nzp[4] + Rl(2) * p + nzm[4];
+        const Rl byz = by * bz, r = rcp_pos(bx * byz);
+        sNx[c] = ax * byz * r;
+        sNy[c] = ay * (bx * bz) * r;
+        nug = az * (bx * by) * r;
+      }
     }
 
     // ---- owned columns, before the barrier: the zeta face between planes s
