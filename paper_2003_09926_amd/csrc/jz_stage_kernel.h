@@ -192,8 +192,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr bool WRITE_R = (MODE & 4) != 0;
   static_assert(TI * TJ + 4 * TI + 4 * TJ + 4 <= NT, "tile roles exceed the workgroup");
 
+  // The middle stages keep each column's own primitives of planes s, s+1
+  // and s+2 (the zeta neighbours and the centre of the gradient plane) in
+  // registers: one plane of primitives in LDS instead of a ring of three, and
+  // 15 fewer LDS reads per flux column.  The first and last stages carry
+  // reductions and have no registers to spare; they keep the ring.
+  constexpr bool ZREG = MODE == 0;
+  constexpr int NPR = ZREG ? 1 : 3;
   // plane buffers (structure of arrays, one slot per tile column, rows of P)
-  __shared__ Rl sPr[3][5][NS];     // ring of three planes of u, v, w, T, p
+  __shared__ Rl sPr[NPR][5][NS];   // u, v, w, T, p: the gradient plane, or a ring of three planes
   __shared__ Rl sQ2[2][5][NS];     // Q of the gradient plane, alternating between two buffers
   __shared__ __attribute__((aligned(16))) Rl sF[10][NS];  // Fhat^xi (rows 0-4), Fhat^eta (rows 5-9)
   Rl(*sFx)[NS] = sF;
@@ -237,14 +244,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const bool q0_is_input = (const void*)A.qin == (const void*)A.q0;
 
   auto node = [&](int k) { return col + plane * map_index(k, A.nk, bk); };
-  auto put_prims = [&](int slot, const Rl q[5]) {
-    if (!isP) return;
+  // primitives u, v, w, T, p of a column's Q, in the order of the sPr rows
+  auto prims_of = [&](const Rl q[5], Rl out[5]) {
     const Prim<Rl> p = primitives(q, gm1, gamma);
-    sPr[slot][0][c] = p.u;
-    sPr[slot][1][c] = p.v;
-    sPr[slot][2][c] = p.w;
-    sPr[slot][3][c] = p.T;
-    sPr[slot][4][c] = p.p;
+    out[0] = p.u;
+    out[1] = p.v;
+    out[2] = p.w;
+    out[3] = p.T;
+    out[4] = p.p;
+  };
+  auto write_prims = [&](int slot, const Rl pr[5]) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sPr[slot][k][c] = pr[k];
   };
 
   // column registers: Q of planes s-1 (m), s, s+1 (g) and the lead s+2 (l)
@@ -264,6 +275,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 
   // ring slots: plane k lives in slot (k - kbeg + 3) % 3
   int slot_s = 1, slot_g = 2, slot_l = 0;  // planes kbeg-2, kbeg-1, kbeg
+  // primitives of this column at planes s (PrM) and s+1 (PrC), carried in
+  // registers when ZREG
+  Rl PrM[5] = {0, 0, 0, 0, 0}, PrC[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int v = 0; v < 5; ++v) Qs[v] = Qg[v] = Qn[v] = Qm[v] = 0;
   if (isP) {
@@ -275,8 +289,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       Qn[v] = (Rl)qin[5 * n2 + v];
     }
     if (isG) met.load(n1, Mn, MJn);
-    put_prims(slot_s, Qs);
-    put_prims(slot_g, Qg);
+    prims_of(Qs, PrM);
+    prims_of(Qg, PrC);
+    if constexpr (!ZREG) {
+      write_prims(slot_s, PrM);
+      write_prims(slot_g, PrC);
+    }
   }
 
   for (int s = kbeg - 2; s < kend; ++s) {
@@ -288,12 +306,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) Qn[v] = (Rl)qin[5 * nn + v];
     }
-    // No barrier here: slot_l was last read in the previous step's gradient
-    // phase (before its second barrier), and Q goes to the other half of sQ2.
-    // The flux, scale and sensor buffers are rewritten only after the next
+    // No barrier here: the primitive plane written now (slot_l; the single
+    // plane when ZREG) was last read in the previous step's gradient phase
+    // (before its second barrier), and Q goes to the other half of sQ2.  The
+    // flux, scale and sensor buffers are rewritten only after the next
     // barrier, which every thread reaches after finishing the owned phase.
     Rl(*sQ)[NS] = sQ2[(s - kbeg) & 1];
-    put_prims(slot_l, Ql);
+    Rl PrL[5] = {0, 0, 0, 0, 0};  // primitives of the lead plane
+    if (isP) {
+      prims_of(Ql, PrL);
+      if constexpr (ZREG) write_prims(0, PrC);  // the gradient plane s+1
+      else write_prims(slot_l, PrL);
+    }
     if (isP) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) sQ[v][c] = Qg[v];
@@ -314,20 +338,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       Jg = move_apart(MJn);
       if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
       const Rl J = (Rl)Jg;
-      const Rl(*Pg)[NS] = sPr[slot_g];
+      const Rl(*Pg)[NS] = sPr[ZREG ? 0 : slot_g];
       // Every primitive this column needs from the three planes, read in one
       // batch: the memory clobber keeps all the reads ahead of the arithmetic,
       // so their latencies overlap instead of adding up.
       Rl ctr[5], nxm[5], nxp[5], nym[5], nyp[5], nzm[5], nzp[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        ctr[q] = Pg[q][c];
         nxm[q] = Pg[q][c - 1];
         nxp[q] = Pg[q][c + 1];
         nym[q] = Pg[q][c - P];
         nyp[q] = Pg[q][c + P];
-        nzm[q] = sPr[slot_s][q][c];
-        nzp[q] = sPr[slot_l][q][c];
+        if constexpr (ZREG) {
+          ctr[q] = PrC[q];
+          nzm[q] = PrM[q];
+          nzp[q] = PrL[q];
+        } else {
+          ctr[q] = Pg[q][c];
+          nzm[q] = sPr[slot_s][q][c];
+          nzp[q] = sPr[slot_l][q][c];
+        }
       }
       asm volatile("" ::: "memory");
       // chain rule d phi / d x_a = J sum_d S^d_a delta_d phi, with the 1/2 of
@@ -546,6 +576,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     slot_s = slot_g;
     slot_g = slot_l;
     slot_l = old_s;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      PrM[k] = PrC[k];
+      PrC[k] = PrL[k];
+    }
   }
 
   // ---- deterministic block reductions (fixed tree order) --------------------
