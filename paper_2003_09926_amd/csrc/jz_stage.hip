@@ -6,7 +6,7 @@ namespace jz {
 
 template <int BX, int BY>
 static hipError_t launch_shape64(const StageArgs& a, const int* flag, int mode, int nblocks, hipStream_t st) {
-  const dim3 grid(nblocks), block(BX * BY);
+  const dim3 grid(nblocks), block(stage_threads<double, BX, BY>());
   switch (mode) {
     case 0: hipLaunchKernelGGL((stage_kernel<double, double, double, false, BX, BY, 0>), grid, block, 0, st, a, flag); break;
     case 1: hipLaunchKernelGGL((stage_kernel<double, double, double, false, BX, BY, 1>), grid, block, 0, st, a, flag); break;
@@ -44,20 +44,20 @@ int stage_wg_per_cu_fp64(int bx, int by) {
   int per_cu = 0;
   hipError_t e = hipErrorInvalidValue;
   if (bx == 32 && by == 16)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 32, 16, 0>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 32, 16, 0>, stage_threads<double, 32, 16>(), 0);
   else if (bx == 64 && by == 8)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 64, 8, 0>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 64, 8, 0>, stage_threads<double, 64, 8>(), 0);
   else if (bx == 16 && by == 32)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 16, 32, 0>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 16, 32, 0>, stage_threads<double, 16, 32>(), 0);
   else if (bx == 32 && by == 8)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 32, 8, 0>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 32, 8, 0>, stage_threads<double, 32, 8>(), 0);
   else if (bx == 16 && by == 16)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 16, 16, 0>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 16, 16, 0>, stage_threads<double, 16, 16>(), 0);
 
   else if (bx == 36 && by == 12)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 36, 12, 0>, 432, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 36, 12, 0>, stage_threads<double, 36, 12>(), 0);
   else if (bx == 20 && by == 20)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 20, 20, 0>, 400, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 20, 20, 0>, stage_threads<double, 20, 20>(), 0);
 
   return e == hipSuccess ? per_cu : 0;
 }
@@ -70,7 +70,7 @@ static hipError_t batch_one64(const BlockDesc* d, const int* off, int nblk, int 
                               int grid_cap, int total_tiles, hipStream_t st) {
   auto kern = stage_batch_kernel<double, double, double, false, BX, BY, MODE>;
   int per_cu = 0, dev = 0, ncu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BX * BY, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, stage_threads<double, BX, BY>(), 0);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
@@ -78,7 +78,7 @@ static hipError_t batch_one64(const BlockDesc* d, const int* off, int nblk, int 
   if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
   if (grid > total_tiles) grid = total_tiles;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(BX * BY), 0, st, d, off, nblk, stage, ns, alpha);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(stage_threads<double, BX, BY>()), 0, st, d, off, nblk, stage, ns, alpha);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ namespace jz {
 //       4 = residual evaluation (double in, double R out)
 template <int BX, int BY>
 static hipError_t launch_shape32(const StageArgs& a, const int* flag, int kind, int nblocks, hipStream_t st) {
-  const dim3 grid(nblocks), block(BX * BY);
+  const dim3 grid(nblocks), block(stage_threads<float, BX, BY>());
   switch (kind) {
     case 0: hipLaunchKernelGGL((stage_kernel<float, double, float, true, BX, BY, 1>), grid, block, 0, st, a, flag); break;
     case 1: hipLaunchKernelGGL((stage_kernel<float, float, float, true, BX, BY, 0>), grid, block, 0, st, a, flag); break;
@@ -64,7 +64,7 @@ static hipError_t batch_one32(const BlockDesc* d, const int* off, int nblk, int 
                               int grid_cap, int total_tiles, hipStream_t st) {
   auto kern = stage_batch_kernel<float, TIn, TOut, true, BX, BY, MODE>;
   int per_cu = 0, dev = 0, ncu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BX * BY, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, stage_threads<float, BX, BY>(), 0);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
@@ -72,7 +72,7 @@ static hipError_t batch_one32(const BlockDesc* d, const int* off, int nblk, int 
   if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
   if (grid > total_tiles) grid = total_tiles;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(BX * BY), 0, st, d, off, nblk, stage, ns, alpha);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(stage_threads<float, BX, BY>()), 0, st, d, off, nblk, stage, ns, alpha);
   return hipGetLastError();
 }
 

@@ -152,6 +152,18 @@ __device__ inline int tile_role(int t, int& tx, int& ty) {
   return role;
 }
 
+// Owned-phase helpers.  In the FP64 shapes with 256 owned columns (four
+// waves, one per SIMD) the workgroup has 512 threads, and thread NI + l is the
+// partner of owned thread l: the same SIMD, otherwise busy only with the
+// halo's primitives and fluxes.  In the owned phase the partner computes the
+// in-plane terms of the last three conserved variables of the owner's column,
+// so that two waves per SIMD share that phase (the owner keeps two, the zeta
+// face and the update).
+template <typename Rl, int BX, int BY>
+constexpr bool stage_helpers() { return sizeof(Rl) == 8 && (BX - 4) * (BY - 4) == 256; }
+template <typename Rl, int BX, int BY>
+constexpr int stage_threads() { return stage_helpers<Rl, BX, BY>() ? 512 : BX * BY; }
+
 // Row pitch (in slots) of the LDS plane buffers of a BX x BY workgroup.  With
 // a pitch of BX, the slots of one tile column lie BX elements apart and the
 // halo threads that walk a column hit the same LDS bank on every row; one
@@ -168,7 +180,8 @@ template <typename Rl, int BX, int BY>
 constexpr int lds_pitch() {
   constexpr long long kLds = 160 * 1024;
   constexpr int waves = sizeof(Rl) == 4 ? 3 : 2;
-  constexpr long long want = (waves * 4 * 64 + BX * BY - 1) / (BX * BY);  // workgroups for that many waves
+  constexpr int nth = stage_threads<Rl, BX, BY>();
+  constexpr long long want = (waves * 4 * 64 + nth - 1) / nth;  // workgroups for that many waves
   constexpr long long fit = kLds / lds_plane_bytes<Rl, BX, BY>(BX);
   return kLds / lds_plane_bytes<Rl, BX, BY>(BX + 1) >= (want < fit ? want : fit) ? BX + 1 : BX;
 }
@@ -183,8 +196,12 @@ constexpr int lds_pitch() {
 // depend on how tiles are scheduled.  Every thread of the workgroup calls it.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
 __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
-  constexpr int NT = BX * BY;
+  constexpr int NT = stage_threads<Rl, BX, BY>();  // threads of the workgroup
   constexpr int TI = BX - 4, TJ = BY - 4;
+  constexpr int NI = TI * TJ;                       // owned columns
+  constexpr bool HELP = stage_helpers<Rl, BX, BY>();
+  constexpr int NV_OWN = HELP ? 2 : 5;              // variables the owner's owned phase computes
+  constexpr int NHV = 5 - NV_OWN;                   // variables its helper computes
   constexpr int P = lds_pitch<Rl, BX, BY>();   // LDS row pitch
   constexpr int NS = (BX - 2) + P * (BY - 1);   // LDS slots per plane buffer
   constexpr bool NORMS = (MODE & 1) != 0;
@@ -207,6 +224,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   Rl(*sFy)[NS] = sF + 5;
   __shared__ Rl sSx[NS], sSy[NS];  // sigma^xi, sigma^eta
   __shared__ Rl sNx[NS], sNy[NS];  // pressure sensor along xi, eta
+  // helpers' in-plane terms of the last two variables, by march-step parity
+  __shared__ Rl sRg[HELP ? 2 : 1][HELP ? NHV : 1][HELP ? NS : 1];
   // end-of-tile reductions reuse the flux buffer (free once the march is done)
   static_assert(sizeof(Rl) * 10 * NS >= sizeof(double) * 2 * NT, "reduction rows exceed the flux buffer");
   double(*sRed)[NT] = reinterpret_cast<double(*)[NT]>(&sF[0][0]);
@@ -233,6 +252,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const bool isP = role <= 2;                     // supplies primitives and Q
   const bool isG = role <= 1;                     // computes fluxes
   const bool isI = role == 0 && ui < A.in.hi[0] && uj < A.in.hi[1];  // owns (writes) its column
+  // the owned column this thread helps with (HELP: thread NI + l helps owned thread l)
+  const int hl = t - NI;
+  const int ch = HELP ? (2 + hl % TI) + P * (2 + hl / TI) : 0;
+  const bool isH = HELP && t >= NI && t < 2 * NI && (i0 + hl % TI) < A.in.hi[0] && (j0 + hl / TI) < A.in.hi[1];
 
   const TIn* __restrict__ qin = (const TIn*)A.qin;
   TOut* __restrict__ qout = (TOut*)A.qout;
@@ -484,47 +507,68 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     }
     __syncthreads();
 
+    // ---- in-plane terms of plane g, one variable per trip, at column slot cc:
+    // variables [vb, ve) rotate into Rr[5 - (ve - vb) .. 4] (no register is
+    // indexed by the trip count)
+    typedef __attribute__((address_space(3))) const Rl* lds_ptr;
+    auto inplane = [&](int cc, int vb, int ve, Rl Rr[5]) {
+      // xi faces cc-1/2 and cc+1/2, eta faces cc-P/2 and cc+P/2 (slots)
+      const Rl e2xp = k2 * fmax(sNx[cc], sNx[cc + 1]);
+      const Rl e2xm = k2 * fmax(sNx[cc - 1], sNx[cc]);
+      const Rl e4xp = fmax(Rl(0), k4 - e2xp), e4xm = fmax(Rl(0), k4 - e2xm);
+      const Rl sgxp = Rl(0.5) * (sSx[cc] + sSx[cc + 1]), sgxm = Rl(0.5) * (sSx[cc - 1] + sSx[cc]);
+      const Rl e2yp = k2 * fmax(sNy[cc], sNy[cc + P]);
+      const Rl e2ym = k2 * fmax(sNy[cc - P], sNy[cc]);
+      const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
+      const Rl sgyp = Rl(0.5) * (sSy[cc] + sSy[cc + P]), sgym = Rl(0.5) * (sSy[cc - P] + sSy[cc]);
+#pragma unroll 1
+      for (int v = vb; v < ve; ++v) {
+        // The empty asm hides the array base, so that every neighbour
+        // access is one base register plus an immediate offset.
+        lds_ptr q = (lds_ptr)&sQ[v][cc - 2 * P];
+        asm volatile("" : "+v"(q));
+        lds_ptr fx = (lds_ptr)&sFx[v][cc - 1];
+        asm volatile("" : "+v"(fx));
+        lds_ptr fy = (lds_ptr)&sFy[v][cc - P];
+        asm volatile("" : "+v"(fy));
+        const Rl q0 = q[2 * P];
+        const Rl qxp = q[2 * P + 1], qxpp = q[2 * P + 2], qxm = q[2 * P - 1], qxmm = q[2 * P - 2];
+        const Rl qyp = q[3 * P], qypp = q[4 * P], qym = q[P], qymm = q[0];
+        const Rl fxm = fx[0], fxp = fx[2], fym = fy[0], fyp = fy[2 * P];
+        asm volatile("" ::: "memory");  // all reads of the trip issued together
+        const Rl dxp = sgxp * (e2xp * (qxp - q0) - e4xp * ((qxpp - qxm) - Rl(3) * (qxp - q0)));
+        const Rl dxm = sgxm * (e2xm * (q0 - qxm) - e4xm * ((qxp - qxmm) - Rl(3) * (q0 - qxm)));
+        const Rl dyp = sgyp * (e2yp * (qyp - q0) - e4yp * ((qypp - qym) - Rl(3) * (qyp - q0)));
+        const Rl dym = sgym * (e2ym * (q0 - qym) - e4ym * ((qyp - qymm) - Rl(3) * (q0 - qym)));
+        const Rl cx = Rl(0.5) * (fxp - fxm);
+        const Rl cy = Rl(0.5) * (fyp - fym);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rr[r] = Rr[r + 1];
+        Rr[4] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
+      }
+    };
+    // sRg buffer written in this march step; the owner reads the other one
+    // (written one step earlier: the terms of its plane s)
+    const int hbuf = (s - kbeg) & 1;
+    if (HELP && isH && s >= kbeg - 1) {
+      Rl Rh[5] = {0, 0, 0, 0, 0};
+      inplane(ch, NV_OWN, 5, Rh);
+#pragma unroll
+      for (int k = 0; k < NHV; ++k) sRg[hbuf][k][ch] = Rh[5 - NHV + k];
+    }
+
     // ---- owned columns: in-plane terms of plane g, residual of plane s ------
     if (own) {
       Rl Rg[5] = {0, 0, 0, 0, 0};
-      {
-        // xi faces c-1/2 and c+1/2, eta faces c-P/2 and c+P/2 (slots)
-        const Rl e2xp = k2 * fmax(sNx[c], sNx[c + 1]);
-        const Rl e2xm = k2 * fmax(sNx[c - 1], sNx[c]);
-        const Rl e4xp = fmax(Rl(0), k4 - e2xp), e4xm = fmax(Rl(0), k4 - e2xm);
-        const Rl sgxp = Rl(0.5) * (sSx[c] + sSx[c + 1]), sgxm = Rl(0.5) * (sSx[c - 1] + sSx[c]);
-        const Rl e2yp = k2 * fmax(sNy[c], sNy[c + P]);
-        const Rl e2ym = k2 * fmax(sNy[c - P], sNy[c]);
-        const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
-        const Rl sgyp = Rl(0.5) * (sSy[c] + sSy[c + P]), sgym = Rl(0.5) * (sSy[c - P] + sSy[c]);
-        // One variable per trip (not unrolled: the unrolled form runs out of
-        // registers).  The results rotate through Rg so that no register is
-        // indexed by the trip count.
-        typedef __attribute__((address_space(3))) const Rl* lds_ptr;
-#pragma unroll 1
-        for (int v = 0; v < 5; ++v) {
-          // The empty asm hides the array base, so that every neighbour
-          // access is one base register plus an immediate offset.
-          lds_ptr q = (lds_ptr)&sQ[v][c - 2 * P];
-          asm volatile("" : "+v"(q));
-          lds_ptr fx = (lds_ptr)&sFx[v][c - 1];
-          asm volatile("" : "+v"(fx));
-          lds_ptr fy = (lds_ptr)&sFy[v][c - P];
-          asm volatile("" : "+v"(fy));
-          const Rl q0 = q[2 * P];
-          const Rl qxp = q[2 * P + 1], qxpp = q[2 * P + 2], qxm = q[2 * P - 1], qxmm = q[2 * P - 2];
-          const Rl qyp = q[3 * P], qypp = q[4 * P], qym = q[P], qymm = q[0];
-          const Rl fxm = fx[0], fxp = fx[2], fym = fy[0], fyp = fy[2 * P];
-          asm volatile("" ::: "memory");  // all reads of the trip issued together
-          const Rl dxp = sgxp * (e2xp * (qxp - q0) - e4xp * ((qxpp - qxm) - Rl(3) * (qxp - q0)));
-          const Rl dxm = sgxm * (e2xm * (q0 - qxm) - e4xm * ((qxp - qxmm) - Rl(3) * (q0 - qxm)));
-          const Rl dyp = sgyp * (e2yp * (qyp - q0) - e4yp * ((qypp - qym) - Rl(3) * (qyp - q0)));
-          const Rl dym = sgym * (e2ym * (q0 - qym) - e4ym * ((qyp - qymm) - Rl(3) * (q0 - qym)));
-          const Rl cx = Rl(0.5) * (fxp - fxm);
-          const Rl cy = Rl(0.5) * (fyp - fym);
+      inplane(c, 0, NV_OWN, Rg);
+      if (HELP) {
+        // the owner's variables sit in Rg[NHV..4]; the helper's terms of
+        // plane s (its variables) complete the carried sum
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Rg[r] = Rg[r + 1];
-          Rg[4] = (cx + cy) - ((dxp - dxm) + (dyp - dym));
+        for (int v = 0; v < NV_OWN; ++v) Rg[v] = Rg[v + NHV];
+        if (s >= kbeg) {
+#pragma unroll
+          for (int k = 0; k < NHV; ++k) Acc[NV_OWN + k] = sRg[hbuf ^ 1][k][c] + Acc[NV_OWN + k];
         }
       }
       if (s >= kbeg) {
@@ -557,8 +601,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
           }
         }
       }
+      // Acc: in-plane terms of plane g minus its lower zeta face; with HELP
+      // the helper's variables arrive next step, so only -Hp is carried
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Acc[v] = Rg[v] - Hp[v];
+      for (int v = 0; v < 5; ++v) Acc[v] = (v < NV_OWN ? Rg[v] : Rl(0)) - Hp[v];
     }
 
     // ---- shift the column registers and the ring by one plane ---------------
@@ -629,8 +675,8 @@ constexpr int stage_waves_per_eu() { return (sizeof(Rl) == 4 && MODE != 3) ? 3 :
 
 // Single block: one workgroup per tile, tiles spread XCD by XCD.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>())))
-void stage_kernel(StageArgs A, const int* __restrict__ flag) {
+__global__ __launch_bounds__((stage_threads<Rl, BX, BY>()))
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
   if (*flag) return;  // a failed step froze the state
   stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -642,8 +688,8 @@ void stage_kernel(StageArgs A, const int* __restrict__ flag) {
 // L2; the workgroups of a slot walk its share with a fixed stride, and every
 // workgroup exits once its share is done.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>())))
-void stage_batch_kernel(const BlockDesc* __restrict__ desc,
+__global__ __launch_bounds__((stage_threads<Rl, BX, BY>()))
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
                                                              const int* __restrict__ tile_off, int nblk,
                                                              int stage, int nstages, double alpha) {
   // at most 8 slots, and never more slots than workgroups, so that every
