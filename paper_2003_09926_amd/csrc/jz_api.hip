@@ -118,12 +118,13 @@ long long interior_count(const Interior& in) {
 
 void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   const bool f32 = p && p->precision == JZ_FP32_FLUX;
-  // defaults measured on the 512 x 256 x 256 workload: 32 owned columns per
-  // tile row (two 16-lane groups, so a row's LDS reads meet no bank conflict);
-  // FP64 32 x 8 tiles (four owned waves, one per SIMD; two waves per SIMD),
-  // FP32-flux 32 x 16 tiles (720 threads, three waves per SIMD)
-  t->bx = 36;
-  t->by = f32 ? 20 : 12;
+  // defaults measured on the 512 x 256 x 256 workload: tile rows of 16 or 32
+  // owned columns (whole 16-lane groups, so a row's LDS reads meet no bank
+  // conflict); FP64 16 x 16 tiles (four owned waves, one per SIMD, and four
+  // partner waves; two waves per SIMD), FP32-flux 32 x 16 tiles (720 threads,
+  // three waves per SIMD)
+  t->bx = f32 ? 36 : 20;
+  t->by = 20;
   if (p && p->tile_i > 0 && p->tile_j > 0) {
     t->bx = p->tile_i + 4;
     t->by = p->tile_j + 4;
