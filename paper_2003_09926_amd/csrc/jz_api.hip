@@ -33,7 +33,7 @@ hipError_t launch_stats_finalize(const double* acc, long long N, double inv_n, d
 hipError_t launch_stats_profile(const double* soa, long long N, int ni, int nj, int nk, int i, const int* bins,
                                 int nbins, double* out, hipStream_t st);
 hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
-                     const int n[3], const int bc[6], double gamma, double mach_inf, hipStream_t st);
+                     const int n[3], const int bc[6], double gamma, double mach_inf, double* axis_mean, hipStream_t st);
 hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, int bnd, void* m, double* jac,
                              bool met32, hipStream_t st);
 hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int axis_ni, int axis_nj, int* flag,
@@ -86,7 +86,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //              floats are the float stage states Q32a, Q32b) | metrics
 //              (9 floats per node) | J (1 double per node)
 struct Layout {
-  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, stats, total;
+  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, stats, axis, total;
   long long np;
 };
 
@@ -195,7 +195,7 @@ int partial_capacity(int ni, int nj, int nk, const Tiling& t) {
   return fine > t.nblocks ? fine : t.nblocks;
 }
 
-Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats) {
+Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats, int axis_ni) {
   Layout L;
   std::memset(&L, 0, sizeof L);
   size_t off = 0;
@@ -222,6 +222,9 @@ Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats) {
   L.flag = take(4 * sizeof(int));
   // time-averaged statistics: sums of u, u^2, p, p^2 per node (node-major)
   L.stats = stats ? take(4 * N * sizeof(double)) : 0;
+  // centreline: the azimuthal mean of the five conserved variables at each
+  // axial station (computed once per stage, read by every axis node)
+  L.axis = axis_ni > 0 ? take((size_t)axis_ni * 5 * sizeof(double)) : 0;
   L.total = off;
   return L;
 }
@@ -347,6 +350,7 @@ struct jz_solver {
   Clock* clock;
   int* flag;
   double* stats;          // sums of u, u^2, p, p^2 per node, or NULL
+  double* axis_mean;      // centreline: azimuthal means per axial station, or NULL
   long long stat_samples; // samples in the sums
   long long stat_steps;   // steps since the last reset (samples every stats_interval)
   // timing
@@ -396,7 +400,8 @@ size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
   if (!params_ok(p, &why) || !dims_ok(ni, nj, nk, p, &why)) return 0;
   Tiling t;
   pick_tiling(ni, nj, nk, p, &t);
-  return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t), p->stats_interval > 0)
+  return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t), p->stats_interval > 0,
+                    p->bc[2] == JZ_BC_AXIS ? ni : 0)
       .total;
 }
 
@@ -420,7 +425,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->in = interior_of(ni, nj, nk, p);
   s->prec = p->precision;
   s->cap = partial_capacity(ni, nj, nk, s->tl);
-  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0);
+  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0, p->bc[2] == JZ_BC_AXIS ? ni : 0);
   s->stream = (hipStream_t)hip_stream;
   s->timing = false;
   s->stage_ms_acc = 0;
@@ -464,6 +469,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   s->clock = (Clock*)(s->ws + s->L.clock);
   s->flag = (int*)(s->ws + s->L.flag);
   s->stats = s->L.stats ? (double*)(s->ws + s->L.stats) : nullptr;
+  s->axis_mean = s->L.axis ? (double*)(s->ws + s->L.axis) : nullptr;
   s->stat_samples = 0;
   s->stat_steps = 0;
   s->grid_set = s->state_set = s->dt_valid = false;
@@ -689,7 +695,7 @@ int jz_advance(jz_solver* s, int nsteps) {
       if (s->in.bnd) {
         const int n[3] = {s->ni, s->nj, s->nk};
         HIP_TRY(launch_bc(out, s->prec == JZ_FP32_FLUX && !last, s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, n,
-                          s->p.bc, s->p.gamma, s->p.mach_inf, s->stream));
+                          s->p.bc, s->p.gamma, s->p.mach_inf, s->axis_mean, s->stream));
       }
       if (s->timing) {
         HIP_TRY(hipEventRecord(e1, s->stream));

@@ -64,12 +64,28 @@ __device__ void farfield_state(double g, double mach_inf, const double qi[5], co
   qb[4] = pb / (g - 1.0) + 0.5 * rb * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
 }
 
+// Centreline: the average over all azimuths of ring j = 2 of each conserved
+// variable at each axial station i, one thread per (i, variable), summed in
+// the order k = 0, 1, ..., nk-1 (the fixed order every axis node uses).
+template <typename T>
+__global__ __launch_bounds__(256) void axis_mean_kernel(const T* __restrict__ q, int ni, int nj, int nk,
+                                                        double* __restrict__ mean) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 5 * ni) return;
+  const int i = t / 5, v = t % 5;
+  const long long row = (long long)ni * nj;
+  const long long base = i + 2LL * ni;  // (i, 2, 0)
+  double acc = 0.0;
+  for (int kk = 0; kk < nk; ++kk) acc += (double)q[5 * (base + kk * row) + v];
+  mean[t] = acc / (double)nk;
+}
+
 // One thread per boundary-layer node of direction d.  Nodes read as
 // references (index 2 or n-3 along d, all azimuths of ring 2 for the
 // centreline) are never written by the same launch.
 template <typename T, bool MET32>
 __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double* __restrict__ q0, MetView<MET32> met,
-                                                 BcArgs b) {
+                                                 const double* __restrict__ axis_mean, BcArgs b) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= b.count) return;
   const int d = b.d, e = (d + 1) % 3, f = (d + 2) % 3;
@@ -97,19 +113,15 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
   if ((lo ? b.bc[2 * d] : b.bc[2 * d + 1]) == 3) {
     // centreline (eta- face, d = 1): ring j = 1 extrapolated from the first
     // advanced ring j = 2 (zeroth order, per azimuth); axis nodes j = 0 set
-    // to the average over all azimuths of that ring, summed in the order
-    // k = 0, 1, ..., nk-1 by every thread alike (fixed order: every axis node
-    // of one i gets the bitwise same value)
-    double acc[5] = {0, 0, 0, 0, 0};
-    const long long row = (long long)b.n[0] * b.n[1];
+    // to the average over all azimuths of that ring (axis_mean_kernel, one
+    // fixed-order sum per axial station: every axis node of one i gets the
+    // bitwise same value)
+    double acc[5];
     if (c[1] == 1) {
       const long long src = node + b.n[0];  // (i, 2, k)
       for (int v = 0; v < 5; ++v) acc[v] = (double)q[5 * src + v];
     } else {
-      const long long base = c[0] + 2LL * b.n[0];  // (i, 2, 0)
-      for (int kk = 0; kk < b.n[2]; ++kk)
-        for (int v = 0; v < 5; ++v) acc[v] += (double)q[5 * (base + kk * row) + v];
-      for (int v = 0; v < 5; ++v) acc[v] /= (double)b.n[2];
+      for (int v = 0; v < 5; ++v) acc[v] = axis_mean[5 * c[0] + v];
     }
     for (int v = 0; v < 5; ++v) q[5 * node + v] = (T)acc[v];
     return;
@@ -135,7 +147,7 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
 
 template <typename T, bool MET32>
 hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double* jac, const int n[3],
-                           const int bc[6], double gamma, double mach_inf, hipStream_t st) {
+                           const int bc[6], double gamma, double mach_inf, double* axis_mean, hipStream_t st) {
   MetView<MET32> mv;
   mv.m = (decltype(mv.m))met;
   mv.jac = jac;
@@ -148,8 +160,17 @@ hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double
     b.gamma = gamma;
     b.mach_inf = mach_inf;
     b.count = 4LL * n[(d + 1) % 3] * n[(d + 2) % 3];
+    if (d == 1 && bc[2] == 3) {
+      // the centreline means, from ring 2 as the xi pass left it
+      if (!axis_mean) return hipErrorInvalidValue;
+      const int mb = (5 * n[0] + 255) / 256;
+      hipLaunchKernelGGL((axis_mean_kernel<T>), dim3(mb), dim3(256), 0, st, (const T*)q, n[0], n[1], n[2], axis_mean);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     const long long blocks = (b.count + 255) / 256;
-    hipLaunchKernelGGL((bc_kernel<T, MET32>), dim3((unsigned)blocks), dim3(256), 0, st, q, q0, mv, b);
+    hipLaunchKernelGGL((bc_kernel<T, MET32>), dim3((unsigned)blocks), dim3(256), 0, st, q, q0, mv,
+                       (const double*)axis_mean, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -159,15 +180,17 @@ hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double
 }  // namespace
 
 // Boundary conditions on the stage state q (node-major; double, or float when
-// q_float), with inflow layers taken from Q(0) = q0.  No-op for a periodic block.
+// q_float), with inflow layers taken from Q(0) = q0.  axis_mean: scratch of
+// 5 x n[0] doubles, required when the eta- face is the centreline.  No-op for
+// a periodic block.
 hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
-                     const int n[3], const int bc[6], double gamma, double mach_inf, hipStream_t st) {
+                     const int n[3], const int bc[6], double gamma, double mach_inf, double* axis_mean, hipStream_t st) {
   if (q_float) {
-    if (met32) return launch_bc_typed<float, true>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
-    return launch_bc_typed<float, false>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
+    if (met32) return launch_bc_typed<float, true>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
+    return launch_bc_typed<float, false>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
   }
-  if (met32) return launch_bc_typed<double, true>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
-  return launch_bc_typed<double, false>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, st);
+  if (met32) return launch_bc_typed<double, true>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
+  return launch_bc_typed<double, false>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
 }
 
 }  // namespace jz
