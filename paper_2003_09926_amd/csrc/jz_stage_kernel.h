@@ -224,7 +224,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   Rl(*sFy)[NS] = sF + 5;
   __shared__ Rl sSx[NS], sSy[NS];  // sigma^xi, sigma^eta
   __shared__ Rl sNx[NS], sNy[NS];  // pressure sensor along xi, eta
-  // helpers' in-plane terms of the last two variables, by march-step parity
+  // helpers' in-plane terms of variables NV_OWN..4 of the owned columns, by march-step parity
   __shared__ Rl sRg[HELP ? 2 : 1][HELP ? NHV : 1][HELP ? NS : 1];
   // end-of-tile reductions reuse the flux buffer (free once the march is done)
   static_assert(sizeof(Rl) * 10 * NS >= sizeof(double) * 2 * NT, "reduction rows exceed the flux buffer");
