@@ -508,8 +508,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     __syncthreads();
 
     // ---- in-plane terms of plane g, one variable per trip, at column slot cc:
-    // variables [vb, ve) rotate into Rr[5 - (ve - vb) .. 4] (no register is
-    // indexed by the trip count)
+    // variables [vb, ve) rotate into Rr[5 - (ve - vb) .. 4].  FP64: the trips
+    // are unrolled (the rotation becomes renaming).  FP32-flux: a rolled loop,
+    // which measured faster there; it keeps no register indexed by the trip
+    // count.
+    constexpr int UNR = sizeof(Rl) == 8 ? 5 : 1;
     typedef __attribute__((address_space(3))) const Rl* lds_ptr;
     auto inplane = [&](int cc, int vb, int ve, Rl Rr[5]) {
       // xi faces cc-1/2 and cc+1/2, eta faces cc-P/2 and cc+P/2 (slots)
@@ -521,7 +524,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       const Rl e2ym = k2 * fmax(sNy[cc - P], sNy[cc]);
       const Rl e4yp = fmax(Rl(0), k4 - e2yp), e4ym = fmax(Rl(0), k4 - e2ym);
       const Rl sgyp = Rl(0.5) * (sSy[cc] + sSy[cc + P]), sgym = Rl(0.5) * (sSy[cc - P] + sSy[cc]);
-#pragma unroll 1
+#pragma unroll UNR
       for (int v = vb; v < ve; ++v) {
         // The empty asm hides the array base, so that every neighbour
         // access is one base register plus an immediate offset.
@@ -557,19 +560,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       for (int k = 0; k < NHV; ++k) sRg[hbuf][k][ch] = Rh[5 - NHV + k];
     }
 
-    // ---- owned columns: in-plane terms of plane g, residual of plane s ------
-    if (own) {
-      Rl Rg[5] = {0, 0, 0, 0, 0};
-      inplane(c, 0, NV_OWN, Rg);
-      if (HELP) {
-        // the owner's variables sit in Rg[NHV..4]; the helper's terms of
-        // plane s (its variables) complete the carried sum
+    // ---- owned columns: residual and update of plane s, in-plane terms of
+    // plane g.  The FP64 form updates first: that frees the update's double
+    // registers before the unrolled trips.  The FP32-flux form, whose rolled
+    // trips give the Q(0) reads of the update more time, updates last.
+    constexpr bool UPDATE_FIRST = sizeof(Rl) == 8;
+    auto update = [&]() {
+      if (HELP && s >= kbeg) {
+        // the helper's terms of plane s (its variables) complete the carried sum
 #pragma unroll
-        for (int v = 0; v < NV_OWN; ++v) Rg[v] = Rg[v + NHV];
-        if (s >= kbeg) {
-#pragma unroll
-          for (int k = 0; k < NHV; ++k) Acc[NV_OWN + k] = sRg[hbuf ^ 1][k][c] + Acc[NV_OWN + k];
-        }
+        for (int k = 0; k < NHV; ++k) Acc[NV_OWN + k] = sRg[hbuf ^ 1][k][c] + Acc[NV_OWN + k];
       }
       if (s >= kbeg) {
         double R[5];
@@ -601,6 +601,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
           }
         }
       }
+    };
+    if (own) {
+      if constexpr (UPDATE_FIRST) update();
+      Rl Rg[5] = {0, 0, 0, 0, 0};
+      inplane(c, 0, NV_OWN, Rg);
+      // the owner's variables sit in Rg[NHV..4]
+      if (HELP) {
+#pragma unroll
+        for (int v = 0; v < NV_OWN; ++v) Rg[v] = Rg[v + NHV];
+      }
+      if constexpr (!UPDATE_FIRST) update();
       // Acc: in-plane terms of plane g minus its lower zeta face; with HELP
       // the helper's variables arrive next step, so only -Hp is carried
 #pragma unroll
