@@ -65,19 +65,36 @@ __device__ void farfield_state(double g, double mach_inf, const double qi[5], co
 }
 
 // Centreline: the average over all azimuths of ring j = 2 of each conserved
-// variable at each axial station i, one thread per (i, variable), summed in
-// the order k = 0, 1, ..., nk-1 (the fixed order every axis node uses).
+// variable at each axial station i, summed in the order k = 0, 1, ..., nk-1
+// (the fixed order every axis node uses).  A workgroup takes AXS stations:
+// its threads stage the ring values of 256 azimuths at a time in LDS (one
+// azimuth per thread, the stations' 5 AXS values contiguous in memory), then
+// one thread per (station, variable) adds them in azimuth order.
+constexpr int AXS = 4;     // axial stations per workgroup
+constexpr int AXK = 256;   // azimuths staged per pass (= threads)
 template <typename T>
-__global__ __launch_bounds__(256) void axis_mean_kernel(const T* __restrict__ q, int ni, int nj, int nk,
+__global__ __launch_bounds__(AXK) void axis_mean_kernel(const T* __restrict__ q, int ni, int nj, int nk,
                                                         double* __restrict__ mean) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 5 * ni) return;
-  const int i = t / 5, v = t % 5;
+  __shared__ double buf[AXK][5 * AXS];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * AXS;
+  const int ns = min(AXS, ni - i0);  // stations of this workgroup
   const long long row = (long long)ni * nj;
-  const long long base = i + 2LL * ni;  // (i, 2, 0)
+  const T* __restrict__ ring = q + 5 * (i0 + 2LL * ni);  // (i0, 2, 0)
   double acc = 0.0;
-  for (int kk = 0; kk < nk; ++kk) acc += (double)q[5 * (base + kk * row) + v];
-  mean[t] = acc / (double)nk;
+  for (int k0 = 0; k0 < nk; k0 += AXK) {
+    const int cnt = min(AXK, nk - k0);
+    if (t < cnt) {
+      const T* __restrict__ p = ring + 5 * (k0 + t) * row;
+      for (int u = 0; u < 5 * ns; ++u) buf[t][u] = (double)p[u];
+    }
+    __syncthreads();
+    if (t < 5 * ns) {
+      for (int kk = 0; kk < cnt; ++kk) acc += buf[kk][t];
+    }
+    __syncthreads();
+  }
+  if (t < 5 * ns) mean[5 * i0 + t] = acc / (double)nk;
 }
 
 // One thread per boundary-layer node of direction d.  Nodes read as
@@ -88,9 +105,20 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
                                                  const double* __restrict__ axis_mean, BcArgs b) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= b.count) return;
-  const int d = b.d, e = (d + 1) % 3, f = (d + 2) % 3;
-  const int layer = (int)(t % 4);
-  const long long r = t / 4;
+  // Consecutive threads take neighbouring nodes in memory: along xi (the
+  // contiguous index) on the eta and zeta faces, the two adjacent layers of
+  // one row on the xi faces.
+  const int d = b.d, e = d == 0 ? 1 : 0, f = d == 2 ? 1 : 2;  // in-face directions, e the faster
+  int layer;
+  long long r;
+  if (d == 0) {
+    layer = (int)(t % 4);
+    r = t / 4;
+  } else {
+    const long long face = (long long)b.n[e] * b.n[f];
+    layer = (int)(t / face);
+    r = t % face;
+  }
   int c[3];
   c[d] = layer < 2 ? layer : b.n[d] - 4 + layer;  // 0, 1, n-2, n-1
   c[e] = (int)(r % b.n[e]);
@@ -163,8 +191,8 @@ hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double
     if (d == 1 && bc[2] == 3) {
       // the centreline means, from ring 2 as the xi pass left it
       if (!axis_mean) return hipErrorInvalidValue;
-      const int mb = (5 * n[0] + 255) / 256;
-      hipLaunchKernelGGL((axis_mean_kernel<T>), dim3(mb), dim3(256), 0, st, (const T*)q, n[0], n[1], n[2], axis_mean);
+      const int mb = (n[0] + AXS - 1) / AXS;
+      hipLaunchKernelGGL((axis_mean_kernel<T>), dim3(mb), dim3(AXK), 0, st, (const T*)q, n[0], n[1], n[2], axis_mean);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
