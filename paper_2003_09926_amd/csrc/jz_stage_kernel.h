@@ -193,8 +193,9 @@ constexpr int lds_pitch() {
 // MODE bit 2: write R itself instead of the stage update
 // One tile (logical index lt of the block described by A) through one stage.
 // Partial norms and lambda maxima go to slot lt, so the reductions do not
-// depend on how tiles are scheduled.  Every thread of the workgroup calls it.
-template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
+// depend on how tiles are scheduled.  Every thread of the workgroup calls it;
+// PERSIST: called from the persistent batch kernel's tile loop.
+template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE, bool PERSIST>
 __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr int NT = stage_threads<Rl, BX, BY>();  // threads of the workgroup
   constexpr int TI = BX - 4, TJ = BY - 4;
@@ -209,12 +210,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr bool WRITE_R = (MODE & 4) != 0;
   static_assert(TI * TJ + 4 * TI + 4 * TJ + 4 <= NT, "tile roles exceed the workgroup");
 
-  // The middle stages keep each column's own primitives of planes s, s+1
-  // and s+2 (the zeta neighbours and the centre of the gradient plane) in
-  // registers: one plane of primitives in LDS instead of a ring of three, and
-  // 15 fewer LDS reads per flux column.  The first and last stages carry
-  // reductions and have no registers to spare; they keep the ring.
-  constexpr bool ZREG = MODE == 0;
+  // The column's own primitives of planes s, s+1 and s+2 (the zeta
+  // neighbours and the centre of the gradient plane) are kept in registers:
+  // one plane of primitives in LDS instead of a ring of three, and 15 fewer
+  // LDS reads per flux column.  Where the registers do not allow it, the
+  // stage keeps the ring: the FP32-flux stages with reductions (at three
+  // waves per SIMD) and, in the batch kernel, whose tile loop holds more
+  // registers, every stage with reductions.
+  constexpr bool ZREG = MODE == 0 || (sizeof(Rl) == 8 && !PERSIST && (MODE == 1 || MODE == 2));
   constexpr int NPR = ZREG ? 1 : 3;
   // plane buffers (structure of arrays, one slot per tile column, rows of P)
   __shared__ Rl sPr[NPR][5][NS];   // u, v, w, T, p: the gradient plane, or a ring of three planes
@@ -689,7 +692,7 @@ template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, 
 __global__ __launch_bounds__((stage_threads<Rl, BX, BY>()))
 __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
   if (*flag) return;  // a failed step froze the state
-  stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, xcd_remap(blockIdx.x, gridDim.x));
+  stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE, false>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Many blocks in one persistent launch.  The tiles of all blocks form one
@@ -743,7 +746,7 @@ __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_
     A.in = D.in;
     A.ph = D.ph;
     __syncthreads();  // the previous tile's LDS readers are done
-    stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE>(A, g - tile_off[a]);
+    stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE, true>(A, g - tile_off[a]);
   }
 }
 
