@@ -163,18 +163,23 @@ template <typename Rl, int BX, int BY>
 constexpr bool stage_helpers() { return sizeof(Rl) == 8 && (BX - 4) * (BY - 4) == 256; }
 template <typename Rl, int BX, int BY>
 constexpr int stage_threads() { return stage_helpers<Rl, BX, BY>() ? 512 : BX * BY; }
+// conserved variables whose in-plane terms the partner computes
+template <typename Rl, int BX, int BY>
+constexpr int stage_helper_vars() { return stage_helpers<Rl, BX, BY>() ? 3 : 0; }
 
 // Row pitch (in slots) of the LDS plane buffers of a BX x BY workgroup.  With
 // a pitch of BX, the slots of one tile column lie BX elements apart and the
 // halo threads that walk a column hit the same LDS bank on every row; one
 // slot of padding per row spreads them over the banks.  The padding is taken
-// where the 39 plane buffers (slots up to the last one a thread uses: ring-2
-// corners have none; 32 bytes of alignment slack) still let the CU hold the
-// workgroups the register budget allows: two waves per SIMD in FP64, three in
-// the FP32-flux form.
+// where the plane buffers of a stage with the primitive ring (39, plus the
+// partners' terms for two march steps; slots up to the last one a thread
+// uses: ring-2 corners have none; 32 bytes of alignment slack) still let the
+// CU hold the workgroups the register budget allows: two waves per SIMD in
+// FP64, three in the FP32-flux form.
 template <typename Rl, int BX, int BY>
 constexpr long long lds_plane_bytes(int pitch) {
-  return 39LL * ((BX - 2) + (long long)pitch * (BY - 1)) * (long long)sizeof(Rl) + 32;
+  return (39LL + 2 * stage_helper_vars<Rl, BX, BY>()) * ((BX - 2) + (long long)pitch * (BY - 1)) *
+             (long long)sizeof(Rl) + 32;
 }
 template <typename Rl, int BX, int BY>
 constexpr int lds_pitch() {
@@ -201,8 +206,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr int TI = BX - 4, TJ = BY - 4;
   constexpr int NI = TI * TJ;                       // owned columns
   constexpr bool HELP = stage_helpers<Rl, BX, BY>();
-  constexpr int NV_OWN = HELP ? 2 : 5;              // variables the owner's owned phase computes
-  constexpr int NHV = 5 - NV_OWN;                   // variables its helper computes
+  constexpr int NHV = stage_helper_vars<Rl, BX, BY>();  // variables its helper computes
+  constexpr int NV_OWN = 5 - NHV;                   // variables the owner's owned phase computes
   constexpr int P = lds_pitch<Rl, BX, BY>();   // LDS row pitch
   constexpr int NS = (BX - 2) + P * (BY - 1);   // LDS slots per plane buffer
   constexpr bool NORMS = (MODE & 1) != 0;
