@@ -128,9 +128,9 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
   // supersonic inflow: a node in the layers of any inflow face is held at
   // its Q(0) value, whichever other faces it belongs to
   bool held = false;
-  for (int e = 0; e < 3; ++e) {
-    if (b.bc[2 * e] == 0) continue;
-    if ((c[e] < 2 && b.bc[2 * e] == 1) || (c[e] > b.n[e] - 3 && b.bc[2 * e + 1] == 1)) held = true;
+  for (int x = 0; x < 3; ++x) {
+    if (b.bc[2 * x] == 0) continue;
+    if ((c[x] < 2 && b.bc[2 * x] == 1) || (c[x] > b.n[x] - 3 && b.bc[2 * x + 1] == 1)) held = true;
   }
   if (held) {
     if ((const void*)q != (const void*)q0) {
