@@ -239,6 +239,40 @@ def test_cylinder_centreline_parity(B):
     assert max(per_var_rel(qg - q, qe - q)) <= TOL_INC
 
 
+def test_cylinder_axis_many_azimuths(B):
+    """Centreline means over more azimuths than one LDS pass holds (264 =
+    256 + 8) and an axial length that leaves the last workgroup of stations
+    partly empty (18 = 4 * 4 + 2): one step against the oracle, axis nodes of
+    one i bitwise equal over the azimuth, in both forms' state types."""
+    _log("cylinder 18x8x264: axis mean over two LDS passes")
+    dims = (18, 8, 264)
+    g, q, bc = I.jet_cylinder_case(dims, seed=9)
+    P = oracle.default_params(bc=bc, re_d=2.0e4)
+    ni, nj, nk = dims
+    qe, _, _, _ = oracle.step(dims, P, g.metrics, q)
+    with B.Solver(dims, B.params_default(bc=bc, re_d=2.0e4)) as s:
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        s.advance(1)
+        qg = s.get_state()
+    assert max(per_var_rel(qg, qe)) <= TOL_STATE
+    assert max(per_var_rel(qg - q, qe - q)) <= TOL_INC
+    axis = qg.reshape(5, nk, nj, ni)[:, :, 0, 2:]
+    assert np.all(axis == axis[:, :1, :])
+    with B.Solver(dims, B.params_default(bc=bc, re_d=2.0e4, precision=B.JZ_FP32_FLUX)) as s:
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        s.advance(1)
+        q32 = s.get_state()
+    axis = q32.reshape(5, nk, nj, ni)[:, :, 0, 2:]
+    assert np.all(axis == axis[:, :1, :])
+    d = q32 - qe
+    mom = np.linalg.norm(qe[1:4])
+    errs = [np.linalg.norm(d[0]) / np.linalg.norm(qe[0])] + [np.linalg.norm(d[v]) / mom for v in (1, 2, 3)] + \
+        [np.linalg.norm(d[4]) / np.linalg.norm(qe[4])]
+    assert max(errs) <= 1e-5
+
+
 def test_cylinder_fp32_flux_form_close_to_oracle(B):
     """FP32-flux form on the cylindrical mesh after 5 steps.  The transverse
     momenta are small next to the axial one (noise only in the core), so the
