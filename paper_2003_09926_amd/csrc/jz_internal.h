@@ -196,9 +196,9 @@ struct MetView<true> {  // node-major, 9 floats per node; J in its own double ar
 };
 
 
-// Block index -> logical tile, so that the consecutive logical tiles (which
-// share halo rows) land on the same XCD and its L2.  Workgroups are dispatched
-// round-robin over the 8 XCDs of an MI355X.
+// Block index -> logical tile, so that consecutive logical tiles (which are
+// neighbours and share halo nodes) land on the same XCD and its L2.
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X.
 __device__ inline int xcd_remap(int b, int nb) {
   constexpr int NX = 8;
   const int q = nb / NX, r = nb % NX;

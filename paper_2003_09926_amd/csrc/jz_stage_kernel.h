@@ -241,10 +241,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const Phys ph = A.ph;
   const Rl gm1 = (Rl)ph.gm1, gamma = (Rl)ph.gamma;
   const Rl k2 = (Rl)ph.k2, k4 = (Rl)ph.k4;
-  const int tile_i = lt % A.tiles_i;
-  const int rest = lt / A.tiles_i;
-  const int tile_j = rest % A.tiles_j;
-  const int chunk = rest / A.tiles_j;
+  // Logical tile order: chunk by chunk, bands of two tile rows, and within a
+  // band the two rows' tiles alternate along xi.  The workgroups that run at
+  // once on one XCD (consecutive logical tiles) then form a patch two tiles
+  // tall, so the halo rows between its two rows are read once into the L2
+  // (about 5 % fewer HBM reads than one tile row per XCD).
+  const int per_chunk = A.tiles_i * A.tiles_j;
+  const int chunk = lt / per_chunk;
+  const int r = lt - chunk * per_chunk;
+  const int band = r / (2 * A.tiles_i);
+  const int rows = min(2, A.tiles_j - 2 * band);  // 1 in a last band of an odd row count
+  const int w = r - band * 2 * A.tiles_i;
+  const int tile_i = w / rows;
+  const int tile_j = 2 * band + w % rows;
   const int i0 = A.in.lo[0] + tile_i * TI, j0 = A.in.lo[1] + tile_j * TJ;
   const int kbeg = A.in.lo[2] + chunk * A.kchunk;
   const int kend = min(kbeg + A.kchunk, A.in.hi[2]);
