@@ -234,6 +234,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   __shared__ Rl sNx[NS], sNy[NS];  // pressure sensor along xi, eta
   // helpers' in-plane terms of variables NV_OWN..4 of the owned columns, by march-step parity
   __shared__ Rl sRg[HELP ? 2 : 1][HELP ? NHV : 1][HELP ? NS : 1];
+  // FP64 last stage (single block): each owned thread keeps the metrics of
+  // its column's gradient plane, which it has in registers for the fluxes,
+  // in its own LDS slots (by plane parity) for the next-dt spectral radius
+  // of that plane's update one march step later, instead of reading them
+  // from memory again; no other thread touches them.  Only where the CU's
+  // LDS holds them beside the plane buffers (29 with the primitives in
+  // registers, and the partners' terms) for as many workgroups as the
+  // registers allow (two waves per SIMD).
+  constexpr long long MET_LDS_WG = (29LL + 2 * NHV) * NS * 8 + 2LL * 10 * NI * 8 + 256;
+  constexpr long long REG_WG = (2 * 4 * 64) / NT > 0 ? (2 * 4 * 64) / NT : 1;
+  constexpr bool MET_LDS = MODE == 2 && sizeof(Rl) == 8 && !PERSIST && MET_LDS_WG * REG_WG <= 160LL * 1024;
+  __shared__ double sMo[MET_LDS ? 2 : 1][MET_LDS ? 10 : 1][MET_LDS ? NI : 1];
   // end-of-tile reductions reuse the flux buffer (free once the march is done)
   static_assert(sizeof(Rl) * 10 * NS >= sizeof(double) * 2 * NT, "reduction rows exceed the flux buffer");
   double(*sRed)[NT] = reinterpret_cast<double(*)[NT]>(&sF[0][0]);
@@ -376,6 +388,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) m[k] = move_apart(Mn[k]);
       Jg = move_apart(MJn);
+      if (MET_LDS && t < NI) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sMo[(s + 1) & 1][k][t] = m[k];
+        sMo[(s + 1) & 1][9][t] = Jg;
+      }
       if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
       const Rl J = (Rl)Jg;
       const Rl(*Pg)[NS] = sPr[ZREG ? 0 : slot_g];
@@ -511,7 +528,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) q0v[v] = A.q0[5 * ns + v];
         }
-        if (LAMMAX) met.load(ns, mo, moJ);
+        if (LAMMAX && !MET_LDS) met.load(ns, mo, moJ);
       }
       const Rl e2 = k2 * fmax(nus, nug);
       const Rl e4 = fmax(Rl(0), k4 - e2);
@@ -608,7 +625,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
           }
 #pragma unroll
           for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)qn[v];
-          if (LAMMAX) lmax = max_nan(lmax, lambda_sum(qn, mo, moJ, ph.gamma));
+          if (LAMMAX) {
+            if (MET_LDS) {
+#pragma unroll
+              for (int k = 0; k < 9; ++k) mo[k] = sMo[s & 1][k][t];
+              moJ = sMo[s & 1][9][t];
+            }
+            lmax = max_nan(lmax, lambda_sum(qn, mo, moJ, ph.gamma));
+          }
         }
         if (NORMS) {
 #pragma unroll
