@@ -219,10 +219,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   // neighbours and the centre of the gradient plane) are kept in registers:
   // one plane of primitives in LDS instead of a ring of three, and 15 fewer
   // LDS reads per flux column.  Where the registers do not allow it, the
-  // stage keeps the ring: the FP32-flux stages with reductions (at three
-  // waves per SIMD) and, in the batch kernel, whose tile loop holds more
+  // stage keeps the ring: the FP32-flux first stage (norms at three waves
+  // per SIMD) and, in the batch kernel, whose tile loop holds more
   // registers, every stage with reductions.
-  constexpr bool ZREG = MODE == 0 || (sizeof(Rl) == 8 && !PERSIST && (MODE == 1 || MODE == 2));
+  constexpr bool ZREG = MODE == 0 || (!PERSIST && (MODE == 2 || (MODE == 1 && sizeof(Rl) == 8)));
   constexpr int NPR = ZREG ? 1 : 3;
   // plane buffers (structure of arrays, one slot per tile column, rows of P)
   __shared__ Rl sPr[NPR][5][NS];   // u, v, w, T, p: the gradient plane, or a ring of three planes
@@ -234,18 +234,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   __shared__ Rl sNx[NS], sNy[NS];  // pressure sensor along xi, eta
   // helpers' in-plane terms of variables NV_OWN..4 of the owned columns, by march-step parity
   __shared__ Rl sRg[HELP ? 2 : 1][HELP ? NHV : 1][HELP ? NS : 1];
-  // FP64 last stage (single block): each owned thread keeps the metrics of
-  // its column's gradient plane, which it has in registers for the fluxes,
-  // in its own LDS slots (by plane parity) for the next-dt spectral radius
-  // of that plane's update one march step later, instead of reading them
-  // from memory again; no other thread touches them.  Only where the CU's
-  // LDS holds them beside the plane buffers (29 with the primitives in
+  // Last stage (single block): each owned thread keeps the metrics of its
+  // column's gradient plane, which it has in registers for the fluxes, in
+  // its own LDS slots (by plane parity) for the next-dt spectral radius of
+  // that plane's update one march step later, instead of reading them from
+  // memory again; no other thread touches them.  Only where the CU's LDS
+  // holds them beside the plane buffers (29 with the primitives in
   // registers, and the partners' terms) for as many workgroups as the
-  // registers allow (two waves per SIMD).
-  constexpr long long MET_LDS_WG = (29LL + 2 * NHV) * NS * 8 + 2LL * 10 * NI * 8 + 256;
-  constexpr long long REG_WG = (2 * 4 * 64) / NT > 0 ? (2 * 4 * 64) / NT : 1;
-  constexpr bool MET_LDS = MODE == 2 && sizeof(Rl) == 8 && !PERSIST && MET_LDS_WG * REG_WG <= 160LL * 1024;
-  __shared__ double sMo[MET_LDS ? 2 : 1][MET_LDS ? 10 : 1][MET_LDS ? NI : 1];
+  // registers allow (two waves per SIMD in FP64, three in the FP32-flux form).
+  typedef typename std::conditional<MET32, float, double>::type MT;  // stored metric type
+  constexpr long long MET_LDS_WG =
+      (29LL + 2 * NHV) * NS * (long long)sizeof(Rl) + 2LL * NI * (9 * (long long)sizeof(MT) + 8) + 256;
+  constexpr long long REG_WAVES = (sizeof(Rl) == 4 ? 3 : 2) * 4 * 64;
+  constexpr long long REG_WG = REG_WAVES / NT > 0 ? REG_WAVES / NT : 1;
+  constexpr bool MET_LDS = MODE == 2 && ZREG && !PERSIST && MET_LDS_WG * REG_WG <= 160LL * 1024;
+  __shared__ MT sMo[MET_LDS ? 2 : 1][MET_LDS ? 9 : 1][MET_LDS ? NI : 1];
+  __shared__ double sMoJ[MET_LDS ? 2 : 1][MET_LDS ? NI : 1];
   // end-of-tile reductions reuse the flux buffer (free once the march is done)
   static_assert(sizeof(Rl) * 10 * NS >= sizeof(double) * 2 * NT, "reduction rows exceed the flux buffer");
   double(*sRed)[NT] = reinterpret_cast<double(*)[NT]>(&sF[0][0]);
@@ -390,8 +394,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       Jg = move_apart(MJn);
       if (MET_LDS && t < NI) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) sMo[(s + 1) & 1][k][t] = m[k];
-        sMo[(s + 1) & 1][9][t] = Jg;
+        for (int k = 0; k < 9; ++k) sMo[(s + 1) & 1][k][t] = (MT)m[k];
+        sMoJ[(s + 1) & 1][t] = Jg;
       }
       if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
       const Rl J = (Rl)Jg;
@@ -519,7 +523,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     const long long ns = node(s);
     constexpr bool Q0_IN_REGS = std::is_same<Rl, double>::value && std::is_same<TIn, double>::value;
     double q0v[5] = {0, 0, 0, 0, 0};
-    typename std::conditional<MET32, float, double>::type mo[9];
+    MT mo[9];
     double moJ = 0.0;
     Rl Hp[5] = {0, 0, 0, 0, 0};
     if (own) {
@@ -629,7 +633,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
             if (MET_LDS) {
 #pragma unroll
               for (int k = 0; k < 9; ++k) mo[k] = sMo[s & 1][k][t];
-              moJ = sMo[s & 1][9][t];
+              moJ = sMoJ[s & 1][t];
             }
             lmax = max_nan(lmax, lambda_sum(qn, mo, moJ, ph.gamma));
           }
