@@ -99,7 +99,8 @@ typedef struct {
   double cfl;          /* Courant number of the global time step (0.5) */
   double dt_fixed;     /* > 0: fixed time step instead of the CFL rule (0) */
   double rk_alpha[5];  /* stage coefficients (1/4, 1/6, 3/8, 1/2, 1) */
-  int n_stages;        /* 1..5 (5) */
+  int n_stages;        /* 1..5 (5); with one stage (forward Euler) the stage writes a
+                          stage buffer that is then copied into the state */
   int precision;       /* jz_precision (JZ_FP64) */
   int tile_i, tile_j;  /* launch shape of the stage kernel; 0 = library default */
   int kchunk;          /* planes marched per workgroup; 0 = chosen by the library for
@@ -185,7 +186,9 @@ int jz_eval_residual(jz_solver* s, double* r, int on_device);
 int jz_eval_dt(jz_solver* s, double* dt, double* lambda_max);
 
 /* Kernel timing with hipEvents on the solver's stream: enable = 1 starts
- * recording each stage-kernel launch of jz_advance, 0 stops.  jz_get_timing
+ * recording each stage-kernel launch of jz_advance, 0 stops (enabling creates
+ * a pool of events up front, so that jz_advance creates none for the first
+ * 640 launches).  jz_get_timing
  * synchronises and returns the summed milliseconds and launch count of the
  * stage kernels since timing was enabled, and the algorithmic HBM bytes of
  * those launches (each array read or written once per stage). */
@@ -239,7 +242,8 @@ int jz_destroy(jz_solver* s);
  * stage count and coefficients, and a tile shape with a batch kernel
  * (FP64: 32x8, 16x16, 28x12, 12x12; FP32-flux: 32x16, 28x20, 28x12, 12x12), and must have their
  * grid and state set.  Each member's results are bitwise those of the member
- * advanced alone with the same tile shape.  The caller keeps ownership of the
+ * advanced alone with the same tile shape.  Members need n_stages >= 2 (JZ_EINVAL
+ * otherwise).  The caller keeps ownership of the
  * members and must not advance them on their own while the batch is in use.
  * hip_stream orders the batch against the caller's work (NULL = null
  * stream); the batch runs on an internal non-blocking stream. */

@@ -353,14 +353,60 @@ struct jz_solver {
   double* axis_mean;      // centreline: azimuthal means per axial station, or NULL
   long long stat_samples; // samples in the sums
   long long stat_steps;   // steps since the last reset (samples every stats_interval)
-  // timing
+  // timing: events recorded around stage launches (ev), and created ones
+  // not in use (ev_free), filled by jz_set_timing so that jz_advance creates
+  // none while it issues work
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   std::vector<double> ev_bytes;
   double stage_ms_acc;
   long long stage_launches_acc;
   double stage_bytes_acc;
 };
+
+namespace {
+
+// Shape, parameters, tiling and workspace layout of a solver (no device work).
+void setup_shape(jz_solver* s, int ni, int nj, int nk, const jz_params* p) {
+  s->ni = ni;
+  s->nj = nj;
+  s->nk = nk;
+  s->N = (long long)ni * nj * nk;
+  s->p = *p;
+  s->ph = make_phys(*p);
+  pick_tiling_for_device(ni, nj, nk, p, &s->tl);
+  s->in = interior_of(ni, nj, nk, p);
+  s->prec = p->precision;
+  s->cap = partial_capacity(ni, nj, nk, s->tl);
+  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0, p->bc[2] == JZ_BC_AXIS ? ni : 0);
+  s->timing = false;
+  s->stage_ms_acc = 0;
+  s->stage_launches_acc = 0;
+  s->stage_bytes_acc = 0;
+}
+
+// Pointers of every array into the workspace s->ws (layout s->L).
+void bind_workspace(jz_solver* s) {
+  s->q0 = (double*)(s->ws + s->L.q0);
+  s->qa = (double*)(s->ws + s->L.stage);
+  s->qb = s->qa + 5 * s->L.np;
+  s->q32a = s->prec == JZ_FP32_FLUX ? (float*)(s->ws + s->L.q32a) : nullptr;
+  s->q32b = s->prec == JZ_FP32_FLUX ? (float*)(s->ws + s->L.q32b) : nullptr;  // both inside the scratch region
+  s->met = (void*)(s->ws + s->L.met);
+  s->jac = s->prec == JZ_FP32_FLUX ? (double*)(s->ws + s->L.jac) : nullptr;
+  s->norm_part = (double*)(s->ws + s->L.norm_part);
+  s->lam_part = (double*)(s->ws + s->L.lam_part);
+  s->clock = (Clock*)(s->ws + s->L.clock);
+  s->flag = (int*)(s->ws + s->L.flag);
+  s->stats = s->L.stats ? (double*)(s->ws + s->L.stats) : nullptr;
+  s->axis_mean = s->L.axis ? (double*)(s->ws + s->L.axis) : nullptr;
+  s->stat_samples = 0;
+  s->stat_steps = 0;
+  s->grid_set = s->state_set = s->dt_valid = false;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -415,22 +461,8 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
   std::string why;
   if (!params_ok(p, &why) || !dims_ok(ni, nj, nk, p, &why)) return fail(JZ_EINVAL, "jz_create: %s", why.c_str());
   jz_solver* s = new jz_solver();
-  s->ni = ni;
-  s->nj = nj;
-  s->nk = nk;
-  s->N = (long long)ni * nj * nk;
-  s->p = *p;
-  s->ph = make_phys(*p);
-  pick_tiling_for_device(ni, nj, nk, p, &s->tl);
-  s->in = interior_of(ni, nj, nk, p);
-  s->prec = p->precision;
-  s->cap = partial_capacity(ni, nj, nk, s->tl);
-  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0, p->bc[2] == JZ_BC_AXIS ? ni : 0);
+  setup_shape(s, ni, nj, nk, p);
   s->stream = (hipStream_t)hip_stream;
-  s->timing = false;
-  s->stage_ms_acc = 0;
-  s->stage_launches_acc = 0;
-  s->stage_bytes_acc = 0;
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) {
     delete s;
@@ -457,22 +489,7 @@ int jz_create(int ni, int nj, int nk, const jz_params* p, void* dev_workspace, s
     s->ws = (char*)ptr;
     s->owns_ws = true;
   }
-  s->q0 = (double*)(s->ws + s->L.q0);
-  s->qa = (double*)(s->ws + s->L.stage);
-  s->qb = s->qa + 5 * s->L.np;
-  s->q32a = s->prec == JZ_FP32_FLUX ? (float*)(s->ws + s->L.q32a) : nullptr;
-  s->q32b = s->prec == JZ_FP32_FLUX ? (float*)(s->ws + s->L.q32b) : nullptr;  // both inside the scratch region
-  s->met = (void*)(s->ws + s->L.met);
-  s->jac = s->prec == JZ_FP32_FLUX ? (double*)(s->ws + s->L.jac) : nullptr;
-  s->norm_part = (double*)(s->ws + s->L.norm_part);
-  s->lam_part = (double*)(s->ws + s->L.lam_part);
-  s->clock = (Clock*)(s->ws + s->L.clock);
-  s->flag = (int*)(s->ws + s->L.flag);
-  s->stats = s->L.stats ? (double*)(s->ws + s->L.stats) : nullptr;
-  s->axis_mean = s->L.axis ? (double*)(s->ws + s->L.axis) : nullptr;
-  s->stat_samples = 0;
-  s->stat_steps = 0;
-  s->grid_set = s->state_set = s->dt_valid = false;
+  bind_workspace(s);
   Clock c0;
   std::memset(&c0, 0, sizeof c0);
   int z[4] = {0, 0, 0, 0};
@@ -667,10 +684,47 @@ static hipError_t launch_stage(jz_solver* s, const StageArgs& a, int k, int ns, 
   return launch_stage_fp32(a, s->flag, kind, s->tl.bx, s->tl.by, s->tl.nblocks, s->stream);
 }
 
-int jz_advance(jz_solver* s, int nsteps) {
-  if (!s) return fail(JZ_EINVAL, "jz_advance: NULL solver");
-  if (nsteps < 0) return fail(JZ_EINVAL, "jz_advance: nsteps < 0");
-  if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_advance: grid and state must be set first");
+// Event pairs for the stage timing come from a pool that jz_set_timing fills
+// (kEventPool pairs); only a run of more launches than that creates events
+// while work is issued.
+constexpr int kEventPool = 640;
+
+static int fill_event_pool(jz_solver* s, int pairs) {
+  while ((int)s->ev_free.size() < pairs) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(JZ_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    s->ev_free.emplace_back(e0, e1);
+  }
+  return JZ_OK;
+}
+
+static int take_event_pair(jz_solver* s, hipEvent_t* e0, hipEvent_t* e1) {
+  if (s->ev_free.empty()) {
+    int rc = fill_event_pool(s, 1);
+    if (rc) return rc;
+  }
+  *e0 = s->ev_free.back().first;
+  *e1 = s->ev_free.back().second;
+  s->ev_free.pop_back();
+  return JZ_OK;
+}
+
+static void destroy_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+  for (auto& pr : v) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  v.clear();
+}
+
+// The steps of jz_advance on a solver whose grid and state are set: every
+// launch on s->stream, no allocation, no synchronisation.
+static int advance_steps(jz_solver* s, int nsteps) {
   int rc = ensure_dt(s);
   if (rc) return rc;
   const int ns = s->p.n_stages;
@@ -683,12 +737,15 @@ int jz_advance(jz_solver* s, int nsteps) {
     void* bufB = s->prec == JZ_FP64 ? (void*)s->qb : (void*)s->q32b;
     for (int k = 0; k < ns; ++k) {
       const bool last = (k == ns - 1);
-      void* out = last ? (void*)s->q0 : ((k % 2 == 0) ? bufA : bufB);
+      // A single stage reads its stencil from Q(0): it writes the double
+      // stage buffer A, which is then copied into Q(0), so that no workgroup
+      // overwrites nodes another one still reads as halo.
+      void* out = (ns == 1) ? (void*)s->qa : last ? (void*)s->q0 : ((k % 2 == 0) ? bufA : bufB);
       StageArgs a = stage_args(s, in, out, s->p.rk_alpha[k]);
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (s->timing) {
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
+        int rc_ev = take_event_pair(s, &e0, &e1);
+        if (rc_ev) return rc_ev;
         HIP_TRY(hipEventRecord(e0, s->stream));
       }
       HIP_TRY(launch_stage(s, a, k, ns, false));
@@ -703,6 +760,8 @@ int jz_advance(jz_solver* s, int nsteps) {
         HIP_TRY(launch_bc(out, s->prec == JZ_FP32_FLUX && !last, s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, n,
                           s->p.bc, s->p.gamma, s->p.mach_inf, s->axis_mean, s->stream));
       }
+      if (ns == 1)
+        HIP_TRY(hipMemcpyAsync(s->q0, s->qa, 5 * s->N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
       in = out;
     }
     HIP_TRY(launch_finalize_step(s->clock, s->norm_part, s->lam_part, s->tl.nblocks, step_ctl(s), s->flag,
@@ -713,6 +772,13 @@ int jz_advance(jz_solver* s, int nsteps) {
     }
   }
   return JZ_OK;
+}
+
+int jz_advance(jz_solver* s, int nsteps) {
+  if (!s) return fail(JZ_EINVAL, "jz_advance: NULL solver");
+  if (nsteps < 0) return fail(JZ_EINVAL, "jz_advance: nsteps < 0");
+  if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_advance: grid and state must be set first");
+  return advance_steps(s, nsteps);
 }
 
 static int check_health(jz_solver* s) {
@@ -865,16 +931,16 @@ int jz_stats_profile(jz_solver* s, int i, const int* bins, int nbins, double* me
 int jz_set_timing(jz_solver* s, int enable) {
   if (!s) return fail(JZ_EINVAL, "jz_set_timing: NULL solver");
   HIP_TRY(hipStreamSynchronize(s->stream));
-  for (auto& pr : s->ev) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
+  // recorded events go back to the pool
+  s->ev_free.insert(s->ev_free.end(), s->ev.begin(), s->ev.end());
   s->ev.clear();
   s->ev_bytes.clear();
   s->stage_ms_acc = 0;
   s->stage_launches_acc = 0;
   s->stage_bytes_acc = 0;
   s->timing = enable != 0;
+  if (s->timing) return fill_event_pool(s, kEventPool);
+  destroy_events(s->ev_free);
   return JZ_OK;
 }
 
@@ -887,9 +953,8 @@ int jz_get_timing(jz_solver* s, double* stage_ms, long long* stage_launches, dou
     s->stage_ms_acc += ms;
     s->stage_launches_acc += 1;
     s->stage_bytes_acc += s->ev_bytes[i];
-    (void)hipEventDestroy(s->ev[i].first);
-    (void)hipEventDestroy(s->ev[i].second);
   }
+  s->ev_free.insert(s->ev_free.end(), s->ev.begin(), s->ev.end());
   s->ev.clear();
   s->ev_bytes.clear();
   if (stage_ms) *stage_ms = s->stage_ms_acc;
@@ -937,10 +1002,8 @@ int jz_get_tiling(jz_solver* s, int* tile_i, int* tile_j, int* kchunk) {
 int jz_destroy(jz_solver* s) {
   if (!s) return JZ_OK;
   (void)hipStreamSynchronize(s->stream);
-  for (auto& pr : s->ev) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
+  destroy_events(s->ev);
+  destroy_events(s->ev_free);
   if (s->owns_ws) (void)hipFree(s->ws);
   delete s;
   return JZ_OK;
@@ -1064,6 +1127,8 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
     jz_solver* s = members[i];
     if (!s) return fail(JZ_EINVAL, "jz_batch_create: NULL member %d", i);
     if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_batch_create: member %d has no grid or state", i);
+    if (s->p.n_stages < 2)
+      return fail(JZ_EINVAL, "jz_batch_create: member %d has a single stage (batches need n_stages >= 2)", i);
     if (s->prec != f->prec || s->p.n_stages != f->p.n_stages || s->tl.bx != f->tl.bx || s->tl.by != f->tl.by)
       return fail(JZ_EINVAL, "jz_batch_create: member %d differs in precision, stage count or tile shape", i);
     for (int k = 0; k < f->p.n_stages; ++k)

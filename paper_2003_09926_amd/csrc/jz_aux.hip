@@ -480,4 +480,5 @@ hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const doubl
   return hipGetLastError();
 }
 
+
 }  // namespace jz

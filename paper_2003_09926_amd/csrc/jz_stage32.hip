@@ -79,7 +79,6 @@ static hipError_t batch_one32(const BlockDesc* d, const int* off, int nblk, int 
 template <int BX, int BY>
 static hipError_t batch_shape32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
                                 int grid_cap, int total, hipStream_t st) {
-  if (ns == 1) return batch_one32<double, double, BX, BY, 3>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   if (stage == 0) return batch_one32<double, float, BX, BY, 1>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   if (stage == ns - 1) return batch_one32<float, double, BX, BY, 2>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   return batch_one32<float, float, BX, BY, 0>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);

@@ -399,6 +399,21 @@ def jet_box_case(dims=(64, 48, 48), mach: float = 1.4, seed: int = 1):
     return g, jet_state(g, mach, seed)
 
 
+def shock_box_case(dims=(40, 24, 20), mach: float = 1.4, seed: int = 3, ratio: float = 4.0):
+    """Periodic jet box [0,4) x [-1.5,1.5)^2 with a slab 1 <= x < 2 of
+    `ratio` times the ambient pressure and twice its density (the jet and its
+    noise unchanged): pressure jumps that start the second-difference branch
+    of the artificial dissipation at once."""
+    g = uniform_box(*dims)
+    q = jet_state(g, mach, seed)
+    rho0 = q[0]
+    u, v, w = q[1] / rho0, q[2] / rho0, q[3] / rho0
+    slab = (g.x >= 1.0) & (g.x < 2.0)
+    rho = np.where(slab, 2.0, 1.0)
+    p = np.where(slab, ratio, 1.0) / GAMMA
+    return g, conserved(rho, u, v, w, p)
+
+
 def stretched_jet_case(dims=(512, 256, 256), mach: float = 1.4, seed: int = 2, stride: int = 1):
     """Separable tanh-stretched jet grid with analytic metrics; ``stride``
     subsamples the grid and the perturbation field together."""

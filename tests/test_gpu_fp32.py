@@ -65,6 +65,24 @@ def test_fp32_error_after_1_and_100_steps(B):
     assert max(err) <= 1e-5
 
 
+def test_fp32_single_stage_against_oracle(B):
+    """n_stages = 1 in the FP32-flux form: double in, double out, written to a
+    stage buffer and copied into the state (the one-step bars)."""
+    print("[gpu-case] fp32 single stage 37x23x19", flush=True)
+    g, q = I.jet_box_case((37, 23, 19), seed=4)
+    P = oracle.default_params(n_stages=1, rk_alpha=[1.0], cfl=0.1)
+    qo = q.copy()
+    with _solver(B, g, q, n_stages=1, rk_alpha=[1.0], cfl=0.1) as s:
+        for step in range(3):
+            q_prev = qo
+            qo, _, _, _ = oracle.step(g.dims, P, g.metrics, qo)
+            s.advance(1)
+            qg = s.get_state()
+            assert max(per_var_rel(qg, qo)) <= 2e-6, step
+            assert max(per_var_rel(qg - q_prev, qo - q_prev)) <= 3e-5, step
+            s.set_state(qo)
+
+
 def test_fp32_tl_metrics_and_reproducibility(B):
     print("[gpu-case] fp32 metrics from coordinates, bitwise repeat", flush=True)
     g = I.wavy_grid(16, 12, 10)

@@ -118,6 +118,55 @@ def test_config1_four_steps_per_step_parity(B):
             s.set_state(qo)
 
 
+def test_shock_state_clamped_dissipation_per_step_parity(B):
+    """A high-pressure slab in the jet box: from the first step the pressure
+    sensor puts eps2 = k2 nu above k4 at the slab faces (so eps4 is clamped to
+    0) and between 0 and k4 next to them.  Three steps, each from the
+    oracle's state, at the state and increment bars."""
+    _log("shock box 40x24x20 three steps (eps2 >= k4)")
+    g, q = I.shock_box_case((40, 24, 20), seed=3)
+    P = oracle.default_params()
+    f = oracle.fields(g.dims, P, g.metrics, q)
+    eps2 = P.k2 * f["nu"][0]
+    assert eps2.max() > 2 * P.k4 and np.any((eps2 > 0.1 * P.k4) & (eps2 < P.k4))
+    qo = q.copy()
+    with _solver(B, g, q) as s:
+        for step in range(3):
+            q_prev = qo
+            qo, _, rms_o, _ = oracle.step(g.dims, P, g.metrics, qo)
+            s.advance(1)
+            qg = s.get_state()
+            rms, _ = s.residual_norms()
+            e_state = per_var_rel(qg, qo)
+            e_inc = per_var_rel(qg - q_prev, qo - q_prev)
+            assert max(e_state) <= TOL_STATE, (step, e_state)
+            assert max(e_inc) <= TOL_INC, (step, e_inc)
+            assert np.allclose(rms, rms_o, rtol=1e-9, atol=0)
+            s.set_state(qo)
+
+
+@pytest.mark.parametrize("dims", [(37, 23, 19), (64, 48, 48)])
+def test_single_stage_per_step_parity(B, dims):
+    """n_stages = 1 (forward Euler, alpha = 1): the stage reads its stencil
+    from Q(0) and must not overwrite it while other workgroups still read it
+    as halo.  Three steps from identical states, FP64 bars."""
+    _log(f"single stage {dims}")
+    g, q = I.jet_box_case(dims, seed=4)
+    P = oracle.default_params(n_stages=1, rk_alpha=[1.0], cfl=0.1)
+    qo = q.copy()
+    with _solver(B, g, q, n_stages=1, rk_alpha=[1.0], cfl=0.1) as s:
+        for step in range(3):
+            q_prev = qo
+            qo, dto, _, _ = oracle.step(g.dims, P, g.metrics, qo)
+            s.advance(1)
+            qg = s.get_state()
+            e_state = per_var_rel(qg, qo)
+            e_inc = per_var_rel(qg - q_prev, qo - q_prev)
+            assert max(e_state) <= TOL_STATE, (step, e_state)
+            assert max(e_inc) <= TOL_INC, (step, e_inc)
+            s.set_state(qo)
+
+
 def test_multi_step_drift_stays_at_roundoff(B):
     _log("jetbox 37x23x19 ten steps free-running")
     g, q = I.jet_box_case((37, 23, 19), seed=5)
