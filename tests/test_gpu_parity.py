@@ -121,17 +121,19 @@ def test_config1_four_steps_per_step_parity(B):
 def test_shock_state_clamped_dissipation_per_step_parity(B):
     """A high-pressure slab in the jet box: from the first step the pressure
     sensor puts eps2 = k2 nu above k4 at the slab faces (so eps4 is clamped to
-    0) and between 0 and k4 next to them.  Three steps, each from the
-    oracle's state, at the state and increment bars."""
+    0), and once the jumps have spread over a few nodes (from the second step)
+    also between 0 and k4 next to them.  Three steps, each from the oracle's
+    state, at the state and increment bars."""
     _log("shock box 40x24x20 three steps (eps2 >= k4)")
     g, q = I.shock_box_case((40, 24, 20), seed=3)
     P = oracle.default_params()
-    f = oracle.fields(g.dims, P, g.metrics, q)
-    eps2 = P.k2 * f["nu"][0]
-    assert eps2.max() > 2 * P.k4 and np.any((eps2 > 0.1 * P.k4) & (eps2 < P.k4))
     qo = q.copy()
     with _solver(B, g, q) as s:
         for step in range(3):
+            eps2 = P.k2 * oracle.fields(g.dims, P, g.metrics, qo)["nu"][0]
+            assert eps2.max() > 2 * P.k4
+            if step > 0:
+                assert np.any((eps2 > 0.1 * P.k4) & (eps2 < P.k4))
             q_prev = qo
             qo, _, rms_o, _ = oracle.step(g.dims, P, g.metrics, qo)
             s.advance(1)
