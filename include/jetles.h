@@ -266,6 +266,37 @@ int jz_batch_get_timing(jz_batch* b, double* step_ms, long long* steps, long lon
 int jz_batch_synchronize(jz_batch* b);
 int jz_batch_destroy(jz_batch* b);
 
+/* ---- steps without device allocation -----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * jz_advance_static runs what jz_create + jz_set_grid_metrics + jz_set_state
+ * + jz_advance(nsteps) would, with the same kernels and launch shape (so the
+ * same results, bitwise), but keeps everything beyond the caller's buffers --
+ * node-major copies of state and metrics, stage buffers, partial sums, clock,
+ * failure flag -- in one static device array of the library,
+ * JZ_STATIC_SCRATCH_BYTES per GPU, which each GPU holds from the time the
+ * library's code is loaded there until the process ends.  It calls no
+ * hipMalloc/hipFree, no memset and no host copy, and never synchronises: all
+ * work is issued on hip_stream (NULL = null stream) and the call returns once
+ * it is queued.
+ *   met:   device, 10 x N metric set (the jz_set_grid_metrics layout), read;
+ *   q:     device, 5 x N state, advanced in place by nsteps steps (>= 0);
+ *   info:  device, 14 doubles or NULL: t, dt of the next step, rms[5],
+ *          linf[5] of the last step's first-stage residual, step count, and
+ *          the failure flag (0 = healthy; otherwise NaN/Inf or dt <= 0 was
+ *          met and the state was left at the failing step);
+ *   p:     parameters as for jz_create; stats_interval must be 0.
+ * Every run starts at t = 0 with dt from the given state.  The inputs are not
+ * validated (a non-positive density or pressure shows up in the flag).
+ * JZ_EINVAL for bad sizes or parameters and when the block needs more than
+ * JZ_STATIC_SCRATCH_BYTES (the need is jz_workspace_bytes of the same block:
+ * up to about 330 k nodes in FP64, 400 k in the FP32-flux form).  Calls on
+ * one GPU share its array and keep no state between them: calls that overlap
+ * on one GPU (other streams or threads) race and give wrong results. */
+#define JZ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int jz_advance_static(int ni, int nj, int nk, const jz_params* p, const double* met, double* q, double* info,
+                      int nsteps, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* jz_last_error(void);
 

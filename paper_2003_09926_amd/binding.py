@@ -96,6 +96,7 @@ def library() -> ctypes.CDLL:
         "jz_batch_get_timing": ([S, ctypes.POINTER(d), ctypes.POINTER(ll), ctypes.POINTER(ll)], i),
         "jz_batch_synchronize": ([S], i),
         "jz_batch_destroy": ([S], i),
+        "jz_advance_static": ([i, i, i, P, dp, dp, dp, i, ctypes.c_void_p], i),
         "jz_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -129,6 +130,29 @@ def params_default(**kw) -> Params:
         else:
             raise KeyError(k)
     return p
+
+
+def advance_static(dims, params: Params, met, q, nsteps: int, info=None, stream=None):
+    """jz_advance_static: nsteps steps of the state q (device tensor, 5 x N
+    float64, advanced in place) on the metric set met (device tensor, 10 x N
+    float64), with the library's static scratch and no device allocation.
+    info: optional device tensor of 14 float64 (clock, norms, step count,
+    flag).  stream: a torch.cuda.Stream (default: the current stream).  The
+    call only queues work."""
+    import torch
+    ni, nj, nk = dims
+    n = ni * nj * nk
+    for name, a, rows in (("met", met, 10), ("q", q, 5)):
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+                and a.numel() == rows * n):
+            raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of {rows} x {n} values")
+    if info is not None and not (isinstance(info, torch.Tensor) and info.is_cuda and info.dtype == torch.float64
+                                 and info.numel() >= 14):
+        raise ValueError("info must be a CUDA float64 tensor of at least 14 values")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(library().jz_advance_static(ni, nj, nk, ctypes.byref(params), met.data_ptr(), q.data_ptr(),
+                                       info.data_ptr() if info is not None else None, int(nsteps),
+                                       ctypes.c_void_p(st.cuda_stream)), "jz_advance_static")
 
 
 def workspace_bytes(dims, params: Optional[Params] = None) -> int:

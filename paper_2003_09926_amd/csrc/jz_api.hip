@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,8 @@ hipError_t launch_lambda_max(const double* q, const void* met, const double* jac
 hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCtl ctl, int* flag, hipStream_t st);
 hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
                                 int* flag, hipStream_t st);
+hipError_t launch_reset_clock(Clock* clk, int* flag, hipStream_t st);
+hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, hipStream_t st);
 }  // namespace jz
 
 using namespace jz;
@@ -1010,6 +1013,86 @@ int jz_destroy(jz_solver* s) {
 }
 
 const char* jz_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ===========================================================================
+// steps without allocation: the library's static device scratch
+// ===========================================================================
+// Node-major copies of the state and metrics, stage buffers, partial sums,
+// clock and flag of jz_advance_static.  Each GPU the library runs on holds
+// its own copy from the time the library's code is loaded there until the
+// process ends.  Host code never passes the array's name to a kernel: it
+// passes the device address hipGetSymbolAddress gave for the current device.
+static __device__ __align__(256) unsigned char scratch[JZ_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on device dev (which is current),
+// looked up once per device.
+int static_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(JZ_EINVAL, "jz_advance_static: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(JZ_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return JZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jz_advance_static(int ni, int nj, int nk, const jz_params* p, const double* met, double* q, double* info,
+                      int nsteps, void* hip_stream) {
+  if (!met || !q) return fail(JZ_EINVAL, "jz_advance_static: NULL argument");
+  if (ni < 1 || nj < 1 || nk < 1)
+    return fail(JZ_EINVAL, "jz_advance_static: sizes must be >= 1 (got %d %d %d)", ni, nj, nk);
+  if (nsteps < 0) return fail(JZ_EINVAL, "jz_advance_static: nsteps < 0");
+  if ((long long)ni * nj > (1LL << 30) || (long long)ni * nj * nk > (1LL << 36))
+    return fail(JZ_EINVAL, "jz_advance_static: block too large");
+  std::string why;
+  if (!params_ok(p, &why) || !dims_ok(ni, nj, nk, p, &why))
+    return fail(JZ_EINVAL, "jz_advance_static: %s", why.c_str());
+  if (p->stats_interval > 0)
+    return fail(JZ_EINVAL, "jz_advance_static: time-averaged statistics need a solver (stats_interval must be 0)");
+  jz_solver s{};
+  setup_shape(&s, ni, nj, nk, p);
+  if (s.L.total > JZ_STATIC_SCRATCH_BYTES)
+    return fail(JZ_EINVAL, "jz_advance_static: a %dx%dx%d block needs %zu bytes of scratch, the static array holds %zu",
+                ni, nj, nk, s.L.total, (size_t)JZ_STATIC_SCRATCH_BYTES);
+  HIP_TRY(hipGetDevice(&s.device));
+  char* base = nullptr;
+  int rc = static_scratch(s.device, &base);
+  if (rc) return rc;
+  s.ws = base;
+  s.owns_ws = false;
+  s.stream = (hipStream_t)hip_stream;
+  bind_workspace(&s);
+  // a run that starts afresh: clock and flag cleared, state and metrics
+  // copied into the scratch layout
+  HIP_TRY(launch_reset_clock(s.clock, s.flag, s.stream));
+  if (s.prec == JZ_FP64)
+    HIP_TRY(launch_soa_to_nodes(met, (double*)s.met, s.N, 10, s.stream));
+  else
+    HIP_TRY(launch_soa_to_met32(met, (float*)s.met, s.jac, s.N, s.stream));
+  HIP_TRY(launch_soa_to_nodes(q, s.q0, s.N, 5, s.stream));
+  s.grid_set = s.state_set = true;
+  rc = advance_steps(&s, nsteps);
+  if (rc) return rc;
+  HIP_TRY(launch_nodes_to_soa(s.q0, q, s.N, 5, s.stream));
+  if (info) HIP_TRY(launch_export_clock(s.clock, s.flag, info, s.stream));
+  return JZ_OK;
+}
 
 }  // extern "C"
 

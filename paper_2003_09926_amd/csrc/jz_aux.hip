@@ -481,4 +481,48 @@ hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const doubl
 }
 
 
+// Clock and failure flag of a run that starts afresh: time 0, step 0, no
+// failure (a kernel rather than a memset or a host copy, so that the work can
+// be captured in a graph).
+__global__ void reset_clock_kernel(Clock* __restrict__ clk, int* __restrict__ flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    Clock c;
+    c.t = 0.0;
+    c.dt = 0.0;
+    c.lam_max = 0.0;
+    for (int v = 0; v < 5; ++v) c.rms[v] = c.linf[v] = 0.0;
+    c.steps = 0;
+    c.flag = 0;
+    c.pad = 0;
+    *clk = c;
+    *flag = 0;
+  }
+}
+
+// Clock and flag as 14 doubles: t, dt of the next step, rms[5], linf[5],
+// steps, flag.
+__global__ void export_clock_kernel(const Clock* __restrict__ clk, const int* __restrict__ flag,
+                                    double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = clk->t;
+    out[1] = clk->dt;
+    for (int v = 0; v < 5; ++v) {
+      out[2 + v] = clk->rms[v];
+      out[7 + v] = clk->linf[v];
+    }
+    out[12] = (double)clk->steps;
+    out[13] = (double)*flag;
+  }
+}
+
+hipError_t launch_reset_clock(Clock* clk, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(reset_clock_kernel, dim3(1), dim3(64), 0, st, clk, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(export_clock_kernel, dim3(1), dim3(64), 0, st, clk, flag, out);
+  return hipGetLastError();
+}
+
 }  // namespace jz
