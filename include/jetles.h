@@ -240,7 +240,7 @@ int jz_destroy(jz_solver* s);
  * stage over the tiles of all members, and one finalize launch; the step is
  * captured once in a hipGraph and replayed.  Members must share precision,
  * stage count and coefficients, and a tile shape with a batch kernel
- * (FP64: 32x8, 16x16, 28x12, 12x12; FP32-flux: 32x16, 28x20, 28x12, 12x12), and must have their
+ * (FP64: 16x12, 32x8, 16x16, 28x12, 12x12; FP32-flux: 32x16, 28x20, 28x12, 12x12), and must have their
  * grid and state set.  Each member's results are bitwise those of the member
  * advanced alone with the same tile shape.  Members need n_stages >= 2 (JZ_EINVAL
  * otherwise).  The caller keeps ownership of the

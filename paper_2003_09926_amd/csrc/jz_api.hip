@@ -123,11 +123,11 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   const bool f32 = p && p->precision == JZ_FP32_FLUX;
   // defaults measured on the 512 x 256 x 256 workload: tile rows of 16 or 32
   // owned columns (whole 16-lane groups, so a row's LDS reads meet no bank
-  // conflict); FP64 16 x 16 tiles (four owned waves, one per SIMD, and four
-  // partner waves; two waves per SIMD), FP32-flux 32 x 16 tiles (720 threads,
-  // three waves per SIMD)
+  // conflict); FP64 16 x 12 tiles in the compact form (256 threads, one
+  // wave per SIMD, two workgroups per CU; 8 % ahead of 16 x 16 tiles with
+  // partner waves), FP32-flux 32 x 16 tiles (720 threads, three waves per SIMD)
   t->bx = f32 ? 36 : 20;
-  t->by = 20;
+  t->by = f32 ? 20 : 16;
   if (p && p->tile_i > 0 && p->tile_j > 0) {
     t->bx = p->tile_i + 4;
     t->by = p->tile_j + 4;
@@ -184,7 +184,11 @@ void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* 
   if (per_cu < 1 || ncu < 1) return;
   const Interior in = interior_of(ni, nj, nk, p);
   const int ek = in.hi[2] - in.lo[2];
-  const int kc = auto_kchunk(t->tiles_i * t->tiles_j, ek, (long long)per_cu * ncu);
+  // The compact FP64 shape (16 x 12 tiles, two workgroups per CU) runs its
+  // workgroups unsynchronised, so the rounds model does not hold for it;
+  // chunks of 64 planes measured best on 512 x 256 x 256 (32: +2 %, 128: +6 %).
+  const bool compact = (!p || p->precision == JZ_FP64) && t->bx == 20 && t->by == 16;
+  const int kc = compact ? (ek < 64 ? ek : 64) : auto_kchunk(t->tiles_i * t->tiles_j, ek, (long long)per_cu * ncu);
   t->kchunk = kc;
   t->nchunks = (ek + kc - 1) / kc;
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
@@ -256,7 +260,7 @@ bool params_ok(const jz_params* p, std::string* why) {
     return false;
   }
   if (p->tile_i > 0 && p->precision == JZ_FP64 && !stage_shape_supported(p->tile_i + 4, p->tile_j + 4)) {
-    *why = "unsupported FP64 tile shape (supported: 28x12, 60x4, 12x28, 28x4, 12x12, 32x8, 16x16)";
+    *why = "unsupported FP64 tile shape (supported: 16x12, 16x16, 28x12, 60x4, 12x28, 28x4, 12x12, 32x8)";
     return false;
   }
   if (p->tile_i > 0 && p->precision == JZ_FP32_FLUX && !stage32_shape_supported(p->tile_i + 4, p->tile_j + 4)) {

@@ -22,7 +22,7 @@ static hipError_t launch_shape64(const StageArgs& a, const int* flag, int mode, 
 bool stage_shape_supported(int bx, int by) {
   return (bx == 32 && by == 16) || (bx == 64 && by == 8) || (bx == 16 && by == 32) ||
          (bx == 32 && by == 8) || (bx == 16 && by == 16) || (bx == 36 && by == 12) ||
-         (bx == 20 && by == 20);
+         (bx == 20 && by == 20) || (bx == 20 && by == 16);
 }
 
 hipError_t launch_stage_fp64(const StageArgs& a, const int* flag, int mode, int bx, int by, int nblocks,
@@ -34,6 +34,7 @@ hipError_t launch_stage_fp64(const StageArgs& a, const int* flag, int mode, int 
   if (bx == 16 && by == 16) return launch_shape64<16, 16>(a, flag, mode, nblocks, st);
   if (bx == 36 && by == 12) return launch_shape64<36, 12>(a, flag, mode, nblocks, st);
   if (bx == 20 && by == 20) return launch_shape64<20, 20>(a, flag, mode, nblocks, st);
+  if (bx == 20 && by == 16) return launch_shape64<20, 16>(a, flag, mode, nblocks, st);
   return hipErrorInvalidValue;
 }
 
@@ -58,6 +59,8 @@ int stage_wg_per_cu_fp64(int bx, int by) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 36, 12, 0>, stage_threads<double, 36, 12>(), 0);
   else if (bx == 20 && by == 20)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 20, 20, 0>, stage_threads<double, 20, 20>(), 0);
+  else if (bx == 20 && by == 16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<double, double, double, false, 20, 16, 0>, stage_threads<double, 20, 16>(), 0);
 
   return e == hipSuccess ? per_cu : 0;
 }
@@ -95,7 +98,8 @@ static hipError_t batch_shape64(const BlockDesc* d, const int* off, int nblk, in
 }
 
 bool batch64_shape_supported(int bx, int by) {
-  return (bx == 32 && by == 16) || (bx == 16 && by == 16) || (bx == 36 && by == 12) || (bx == 20 && by == 20);
+  return (bx == 32 && by == 16) || (bx == 16 && by == 16) || (bx == 36 && by == 12) || (bx == 20 && by == 20) ||
+         (bx == 20 && by == 16);
 }
 
 hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
@@ -104,6 +108,7 @@ hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, int nblk,
   if (bx == 16 && by == 16) return batch_shape64<16, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   if (bx == 36 && by == 12) return batch_shape64<36, 12>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   if (bx == 20 && by == 20) return batch_shape64<20, 20>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
+  if (bx == 20 && by == 16) return batch_shape64<20, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
   return hipErrorInvalidValue;
 }
 

@@ -51,6 +51,7 @@
 //              CFL reduction stay double.
 #pragma once
 
+#include <stdint.h>
 #include <type_traits>
 #include "jz_internal.h"
 
@@ -152,6 +153,43 @@ __device__ inline int tile_role(int t, int& tx, int& ty) {
   return role;
 }
 
+// Role of thread t in the compact form: t < TI TJ owns a column; the next
+// 2 TI + 2 TJ threads are the first-ring edge nodes (role 1, in the order of
+// tile_role) and also carry the second-ring node (tx2, ty2) outward of their
+// edge; the next four the first-ring corners (role 2); the rest are idle.
+template <int TI, int TJ>
+__device__ inline int tile_role_compact(int t, int& tx, int& ty, int& tx2, int& ty2) {
+  constexpr int NI = TI * TJ;
+  tx2 = ty2 = 0;
+  if (t < NI) {
+    tx = 2 + t % TI;
+    ty = 2 + t / TI;
+    return 0;
+  }
+  int r = t - NI;
+  if (r < 2 * TI) {
+    tx = tx2 = 2 + r % TI;
+    ty = r < TI ? 1 : TJ + 2;
+    ty2 = r < TI ? 0 : TJ + 3;
+    return 1;
+  }
+  r -= 2 * TI;
+  if (r < 2 * TJ) {
+    ty = ty2 = 2 + r % TJ;
+    tx = r < TJ ? 1 : TI + 2;
+    tx2 = r < TJ ? 0 : TI + 3;
+    return 1;
+  }
+  r -= 2 * TJ;
+  if (r < 4) {
+    tx = (r & 1) ? TI + 2 : 1;
+    ty = (r & 2) ? TJ + 2 : 1;
+    return 2;
+  }
+  tx = ty = 0;
+  return 3;
+}
+
 // Owned-phase helpers.  In the FP64 shapes with 256 owned columns (four
 // waves, one per SIMD) the workgroup has 512 threads, and thread NI + l is the
 // partner of owned thread l: the same SIMD, otherwise busy only with the
@@ -161,8 +199,19 @@ __device__ inline int tile_role(int t, int& tx, int& ty) {
 // face and the update).
 template <typename Rl, int BX, int BY>
 constexpr bool stage_helpers() { return sizeof(Rl) == 8 && (BX - 4) * (BY - 4) == 256; }
+// Compact form (FP64 tiles of 16 x 12 owned columns): 256 threads, one wave
+// per SIMD.  The 192 owned columns and the 56 first-ring edge nodes fill the
+// four waves, so every SIMD runs exactly one flux stream per plane; each edge
+// thread also supplies the second-ring node outward of its edge (primitives
+// and Q only), and four threads the first-ring corners.  At two waves per
+// SIMD a CU holds two such workgroups, whose barriers and latencies then
+// overlap with the other's work.
 template <typename Rl, int BX, int BY>
-constexpr int stage_threads() { return stage_helpers<Rl, BX, BY>() ? 512 : BX * BY; }
+constexpr bool stage_compact() { return sizeof(Rl) == 8 && BX == 20 && BY == 16; }
+template <typename Rl, int BX, int BY>
+constexpr int stage_threads() {
+  return stage_compact<Rl, BX, BY>() ? 256 : stage_helpers<Rl, BX, BY>() ? 512 : BX * BY;
+}
 // conserved variables whose in-plane terms the partner computes
 template <typename Rl, int BX, int BY>
 constexpr int stage_helper_vars() { return stage_helpers<Rl, BX, BY>() ? 3 : 0; }
@@ -213,7 +262,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr bool NORMS = (MODE & 1) != 0;
   constexpr bool LAMMAX = (MODE & 2) != 0;
   constexpr bool WRITE_R = (MODE & 4) != 0;
-  static_assert(TI * TJ + 4 * TI + 4 * TJ + 4 <= NT, "tile roles exceed the workgroup");
+  constexpr bool COMPACT = stage_compact<Rl, BX, BY>();
+  static_assert(COMPACT ? NI + 2 * TI + 2 * TJ + 4 <= NT : TI * TJ + 4 * TI + 4 * TJ + 4 <= NT,
+                "tile roles exceed the workgroup");
 
   // The column's own primitives of planes s, s+1 and s+2 (the zeta
   // neighbours and the centre of the gradient plane) are kept in registers:
@@ -226,7 +277,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr int NPR = ZREG ? 1 : 3;
   // plane buffers (structure of arrays, one slot per tile column, rows of P)
   __shared__ Rl sPr[NPR][5][NS];   // u, v, w, T, p: the gradient plane, or a ring of three planes
-  __shared__ Rl sQ2[2][5][NS];     // Q of the gradient plane, alternating between two buffers
+  // Q of the gradient plane, read in the owned phase after the second
+  // barrier.  The compact form, whose LDS must hold two workgroups, keeps one
+  // buffer and writes it after the first barrier of a march step (by then
+  // every thread has finished reading the previous plane's Q); the other
+  // shapes write before that barrier, alternating between two buffers.
+  constexpr int NQB = COMPACT ? 1 : 2;
+  __shared__ Rl sQ2[NQB][5][NS];
   __shared__ __attribute__((aligned(16))) Rl sF[10][NS];  // Fhat^xi (rows 0-4), Fhat^eta (rows 5-9)
   Rl(*sFx)[NS] = sF;
   Rl(*sFy)[NS] = sF + 5;
@@ -244,12 +301,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   // registers allow (two waves per SIMD in FP64, three in the FP32-flux form).
   typedef typename std::conditional<MET32, float, double>::type MT;  // stored metric type
   constexpr long long MET_LDS_WG =
-      (29LL + 2 * NHV) * NS * (long long)sizeof(Rl) + 2LL * NI * (9 * (long long)sizeof(MT) + 8) + 256;
+      (19LL + 5 * NQB + 2 * NHV) * NS * (long long)sizeof(Rl) + 2LL * NI * (9 * (long long)sizeof(MT) + 8) + 256;
   constexpr long long REG_WAVES = (sizeof(Rl) == 4 ? 3 : 2) * 4 * 64;
   constexpr long long REG_WG = REG_WAVES / NT > 0 ? REG_WAVES / NT : 1;
   constexpr bool MET_LDS = MODE == 2 && ZREG && !PERSIST && MET_LDS_WG * REG_WG <= 160LL * 1024;
   __shared__ MT sMo[MET_LDS ? 2 : 1][MET_LDS ? 9 : 1][MET_LDS ? NI : 1];
   __shared__ double sMoJ[MET_LDS ? 2 : 1][MET_LDS ? NI : 1];
+  // Compact form: Q of the next gradient plane of each edge thread's
+  // second-ring column goes straight from memory into LDS, without registers
+  // (kept in registers, its loads would share them with the owned columns'
+  // values, and the compiler, which cannot tell lanes apart, would then wait
+  // for every load in flight at each march step).  Lane l of the edge wave
+  // loads 4-byte word d of its node into sQB[d][l].  The loads are issued in
+  // inline assembly right after the metric prefetch of the gradient phase:
+  // the compiler does not see them, and none of its own loads issued before
+  // that point is waited for until the next march step, by which time these
+  // have landed; their reader waits for them explicitly (s_waitcnt vmcnt(0))
+  // at the top of the next march step, before anything newer is issued.
+  __shared__ uint32_t sQB[COMPACT ? 10 : 1][COMPACT ? 64 : 1];
   // end-of-tile reductions reuse the flux buffer (free once the march is done)
   static_assert(sizeof(Rl) * 10 * NS >= sizeof(double) * 2 * NT, "reduction rows exceed the flux buffer");
   double(*sRed)[NT] = reinterpret_cast<double(*)[NT]>(&sF[0][0]);
@@ -275,14 +344,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const int kend = min(kbeg + A.kchunk, A.in.hi[2]);
 
   const int t = threadIdx.x;
-  int tx, ty;
-  const int role = tile_role<TI, TJ>(t, tx, ty);
+  int tx, ty, tx2 = 0, ty2 = 0;
+  const int role = COMPACT ? tile_role_compact<TI, TJ>(t, tx, ty, tx2, ty2) : tile_role<TI, TJ>(t, tx, ty);
   const int c = tx + P * ty;                      // LDS slot of this column
   const int ui = i0 - 2 + tx, uj = j0 - 2 + ty;  // unwrapped column indices
   const bool bi = A.in.bnd & 1, bj = A.in.bnd & 2, bk = A.in.bnd & 4;
   const long long col = (long long)map_index(ui, A.ni, bi) + (long long)A.ni * map_index(uj, A.nj, bj);
   const long long plane = (long long)A.ni * A.nj;
-  const bool isP = role <= 2;                     // supplies primitives and Q
+  // compact form: the second-ring column an edge thread supplies (slot cB)
+  const bool hasB = COMPACT && role == 1;
+  const int cB = tx2 + P * ty2;
+  const long long colB = COMPACT ? (long long)map_index(i0 - 2 + tx2, A.ni, bi) +
+                                       (long long)A.ni * map_index(j0 - 2 + ty2, A.nj, bj)
+                                 : 0;
+  // supplies primitives and Q.  In the compact form the four idle threads
+  // do too, for the never-read second-ring corner slot (0, 0): then every
+  // lane issues the same prefetch loads (see below).
+  const bool isP = role <= 2 || COMPACT;
   const bool isG = role <= 1;                     // computes fluxes
   const bool isI = role == 0 && ui < A.in.hi[0] && uj < A.in.hi[1];  // owns (writes) its column
   // the owned column this thread helps with (HELP: thread NI + l helps owned thread l)
@@ -300,6 +378,36 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   const bool q0_is_input = (const void*)A.qin == (const void*)A.q0;
 
   auto node = [&](int k) { return col + plane * map_index(k, A.nk, bk); };
+  auto nodeB = [&](int k) { return colB + plane * map_index(k, A.nk, bk); };
+  typedef __attribute__((address_space(3))) uint32_t* lds_u32;
+  // the ten 4-byte words of the five doubles at src, lane by lane, into rows
+  // of `pitch` words starting at LDS byte address base (uniform per wave)
+  auto dma_q = [&](const double* src, uint32_t base, int pitch) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+    // earlier reads of the buffer by this wave are complete
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int d = 0; d < 10; ++d)
+      asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off"
+                   :
+                   : "s"(base + d * pitch * 4), "v"(w + d)
+                   : "memory");
+  };
+  // five doubles of this lane from such a buffer
+  auto lds_q = [&](const uint32_t* row0, int pitch, int lane, Rl out[5]) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const uint64_t lo = row0[2 * v * pitch + lane], hi = row0[(2 * v + 1) * pitch + lane];
+      out[v] = (Rl)__builtin_bit_cast(double, (hi << 32) | lo);
+    }
+  };
+  // Q of plane k of an edge thread's second-ring column into sQB
+  auto qb_fetch = [&](int k) {
+    if constexpr (COMPACT)
+      dma_q(reinterpret_cast<const double*>(qin) + 5 * nodeB(k),
+            __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_u32)&sQB[0][0]), 64);
+  };
+  const int laneB = t - NI;   // an edge thread's column in sQB
   // primitives u, v, w, T, p of a column's Q, in the order of the sPr rows
   auto prims_of = [&](const Rl q[5], Rl out[5]) {
     const Prim<Rl> p = primitives(q, gm1, gamma);
@@ -344,7 +452,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       Qg[v] = (Rl)qin[5 * n1 + v];
       Qn[v] = (Rl)qin[5 * n2 + v];
     }
-    if (isG) met.load(n1, Mn, MJn);
+    if (COMPACT || isG) met.load(n1, Mn, MJn);
     prims_of(Qs, PrM);
     prims_of(Qg, PrC);
     if constexpr (!ZREG) {
@@ -352,52 +460,107 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       write_prims(slot_g, PrC);
     }
   }
+  // the second-ring column's first gradient plane
+  if (hasB) qb_fetch(kbeg - 1);
 
   for (int s = kbeg - 2; s < kend; ++s) {
     // ---- lead plane s+2 (prefetched); prefetch plane s+3 -------------------
 #pragma unroll
     for (int v = 0; v < 5; ++v) Ql[v] = Qn[v];
-    if (isP && s + 3 < kend + 2) {
-      const long long nn = node(s + 3);
+    // the second-ring column's gradient plane s+1, fetched during the
+    // previous march step's gradient phase: nothing was issued after it
+    if (hasB) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      Rl qb[5], pb[5];
+      lds_q(&sQB[0][0], 64, laneB, qb);
+      prims_of(qb, pb);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) sPr[ZREG ? 0 : slot_g][k][cB] = pb[k];
+    }
+    // The compact form prefetches on every lane and, past the end of the
+    // chunk, reloads the last plane it needs: the same loads on every path
+    // let the compiler count them when it waits for older loads, instead of
+    // assuming they were skipped and waiting for everything in flight.
+    if (isP && (COMPACT || s + 3 < kend + 2)) {
+      const long long nn = node(COMPACT ? min(s + 3, kend + 1) : s + 3);
 #pragma unroll
       for (int v = 0; v < 5; ++v) Qn[v] = (Rl)qin[5 * nn + v];
     }
     // No barrier here: the primitive plane written now (slot_l; the single
     // plane when ZREG) was last read in the previous step's gradient phase
-    // (before its second barrier), and Q goes to the other half of sQ2.  The
-    // flux, scale and sensor buffers are rewritten only after the next
-    // barrier, which every thread reaches after finishing the owned phase.
-    Rl(*sQ)[NS] = sQ2[(s - kbeg) & 1];
+    // (before its second barrier).  The Q, flux, scale and sensor buffers are
+    // rewritten only after the next barrier, which every thread reaches after
+    // finishing the owned phase.
+    Rl(*sQ)[NS] = sQ2[NQB == 2 ? (s - kbeg) & 1 : 0];
+    auto write_q = [&]() {
+      if (isP) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sQ[v][c] = Qg[v];
+      }
+      if (hasB) {
+        Rl qb[5];
+        lds_q(&sQB[0][0], 64, laneB, qb);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sQ[v][cB] = qb[v];
+      }
+    };
     Rl PrL[5] = {0, 0, 0, 0, 0};  // primitives of the lead plane
     if (isP) {
       prims_of(Ql, PrL);
       if constexpr (ZREG) write_prims(0, PrC);  // the gradient plane s+1
       else write_prims(slot_l, PrL);
     }
-    if (isP) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sQ[v][c] = Qg[v];
-    }
+    if constexpr (NQB == 2) write_q();
     __syncthreads();
+    if constexpr (NQB == 1) write_q();
 
     // ---- gradient plane g = s+1: fluxes, dissipation scales, sensors ------
     Rl Fzg[5] = {0, 0, 0, 0, 0}, sigg = 0, nug = 0;
     double Jg = 0.0;
-    if (isG) {
-      // Take the prefetched metrics out of the prefetch registers (into other
-      // registers: the early-clobber move keeps the two apart), so that the
-      // prefetch for the next plane can land in place and is waited for only
-      // where it is used, one march step later.
-      Rl m[9];
+    // Take the prefetched metrics out of the prefetch registers (into other
+    // registers: the early-clobber move keeps the two apart), so that the
+    // prefetch for the next plane can land in place and is waited for only
+    // where it is used, one march step later.  The compact form does this on
+    // every lane, as its lead-plane prefetch.
+    // Q(0) (and, in the last stage, the metrics for the next-dt spectral
+    // radius) of the node this column updates in the owned phase: the middle
+    // stages of the compact form issue these loads as soon as the flux
+    // contraction has freed its registers, the other stages and shapes (whose
+    // registers do not allow that) just before the second barrier
+    const long long ns = node(s);
+    constexpr bool Q0_IN_REGS = std::is_same<Rl, double>::value && std::is_same<TIn, double>::value;
+    double q0v[5] = {0, 0, 0, 0, 0};
+    MT mo[9];
+    double moJ = 0.0;
+    const bool upd = isI && s >= kbeg && !WRITE_R;  // plane s is updated in this step
+    auto update_loads = [&]() {
+      if (!(Q0_IN_REGS && q0_is_input)) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q0v[v] = A.q0[5 * ns + v];
+      }
+      if (LAMMAX && !MET_LDS) met.load(ns, mo, moJ);
+    };
+    Rl m[9];
+    if constexpr (COMPACT) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) m[k] = move_apart(Mn[k]);
       Jg = move_apart(MJn);
-      if (MET_LDS && t < NI) {
+      met.load(node(min(s + 2, kend)), Mn, MJn);
+      // the second-ring column's next gradient plane, straight into LDS
+      if (hasB && s + 1 < kend) qb_fetch(s + 2);
+    }
+    if (isG) {
+      if constexpr (!COMPACT) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) sMo[(s + 1) & 1][k][t] = (MT)m[k];
-        sMoJ[(s + 1) & 1][t] = Jg;
+        for (int k = 0; k < 9; ++k) m[k] = move_apart(Mn[k]);
+        Jg = move_apart(MJn);
+        if (MET_LDS && t < NI) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) sMo[(s + 1) & 1][k][t] = (MT)m[k];
+          sMoJ[(s + 1) & 1][t] = Jg;
+        }
+        if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
       }
-      if (s + 2 < kend + 1) met.load(node(s + 2), Mn, MJn);
       const Rl J = (Rl)Jg;
       const Rl(*Pg)[NS] = sPr[ZREG ? 0 : slot_g];
       // Every primitive this column needs from the three planes, read in one
@@ -472,6 +635,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
         sFy[v][c] = F[1][v];
         Fzg[v] = F[2][v];
       }
+      if constexpr (COMPACT && MODE == 0) {
+        if (upd) update_loads();
+      }
       // spectral radii and anisotropic dissipation scales
       Rl lam[3];
 #pragma unroll
@@ -516,23 +682,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     }
 
     // ---- owned columns, before the barrier: the zeta face between planes s
-    // and s+1 needs only the column's registers, and the global reads for the
-    // update of plane s (Q(0); the metrics for the next-dt spectral radius)
-    // are started here so that their latency overlaps the in-plane work.
+    // and s+1 needs only the column's registers (and the update loads start
+    // here in the shapes other than the compact one)
     const bool own = isI && s >= kbeg - 1;  // plane kbeg-1 is not written
-    const long long ns = node(s);
-    constexpr bool Q0_IN_REGS = std::is_same<Rl, double>::value && std::is_same<TIn, double>::value;
-    double q0v[5] = {0, 0, 0, 0, 0};
-    MT mo[9];
-    double moJ = 0.0;
     Rl Hp[5] = {0, 0, 0, 0, 0};
     if (own) {
-      if (!WRITE_R && s >= kbeg) {
-        if (!(Q0_IN_REGS && q0_is_input)) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) q0v[v] = A.q0[5 * ns + v];
-        }
-        if (LAMMAX && !MET_LDS) met.load(ns, mo, moJ);
+      if constexpr (!(COMPACT && MODE == 0)) {
+        if (upd) update_loads();
       }
       const Rl e2 = k2 * fmax(nus, nug);
       const Rl e4 = fmax(Rl(0), k4 - e2);
@@ -725,14 +881,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 
 // Waves per SIMD the register allocation must allow: the FP32-flux stages fit
 // three (at most 168 VGPRs) except the single-stage form, which carries both
-// reductions; FP64 leaves it to the compiler (two fit).
-template <typename Rl, int MODE>
-constexpr int stage_waves_per_eu() { return (sizeof(Rl) == 4 && MODE != 3) ? 3 : 1; }
+// reductions; the compact FP64 form two (its workgroup has one wave per SIMD,
+// and a CU holds two workgroups); the other FP64 shapes leave it to the
+// compiler (their 512 threads put two waves on every SIMD).
+template <typename Rl, int BX, int BY, int MODE>
+constexpr int stage_waves_per_eu() {
+  return (sizeof(Rl) == 4 && MODE != 3) ? 3 : stage_compact<Rl, BX, BY>() ? 2 : 1;
+}
 
 // Single block: one workgroup per tile, tiles spread XCD by XCD.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
 __global__ __launch_bounds__((stage_threads<Rl, BX, BY>()))
-__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, BX, BY, MODE>()))) void stage_kernel(StageArgs A, const int* __restrict__ flag) {
   if (*flag) return;  // a failed step froze the state
   stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE, false>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -745,7 +905,7 @@ __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_
 // workgroup exits once its share is done.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
 __global__ __launch_bounds__((stage_threads<Rl, BX, BY>()))
-__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, MODE>()))) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, BX, BY, MODE>()))) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
                                                              const int* __restrict__ tile_off, int nblk,
                                                              int stage, int nstages, double alpha) {
   // at most 8 slots, and never more slots than workgroups, so that every
