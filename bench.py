@@ -49,27 +49,54 @@ def _traffic(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(min_seconds: float = 10.0):
-    """The oracle, as it stands, on the stride-4 subsample of the workload
-    (128 x 64 x 64 nodes, same grid family and jet), stepped until at least
-    ``min_seconds`` have elapsed."""
+    """The oracle, as it stands (plain FP64 C++, -O3, OpenMP over outer
+    loops), on the host cores: the stride-4 subsample of the workload (128 x
+    64 x 64 nodes, same grid family and jet) stepped for at least
+    ``min_seconds`` on all cores (the reported value), then for a few steps on
+    one thread; and the 64 x 48 x 48 jet box (4 steps) on all cores."""
     import oracle
     from paper_2003_09926_amd import inputs as I
+
+    def timed(dims, P, m, q, min_s, min_steps):
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            q, _, _, _ = oracle.step(dims, P, m, q)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= min_s and steps >= min_steps:
+                return steps, el
+
+    all_cores = oracle.threads(0)
     g, q = I.stretched_jet_case(DIMS, seed=2, stride=4)
     P = oracle.default_params(re_d=1.0e6)
     oracle.step(g.dims, P, g.metrics, q)          # warm (page-in, thread pool)
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        q, _, _, _ = oracle.step(g.dims, P, g.metrics, q)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds and steps >= 2:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": g.n * 5 * steps / el, "unit": "point-stage updates/s", "cores": cores,
-            "kind": "oracle",
+    steps, el = timed(g.dims, P, g.metrics, q, min_seconds, 2)
+    oracle.threads(1)
+    steps1, el1 = timed(g.dims, P, g.metrics, q, 0.0, 2)
+    oracle.threads(all_cores)
+    gb, qb = I.jet_box_case((64, 48, 48), seed=1)
+    Pb = oracle.default_params()
+    oracle.step(gb.dims, Pb, gb.metrics, qb)
+    steps_b, el_b = timed(gb.dims, Pb, gb.metrics, qb, 0.0, 4)
+    return {"value": g.n * 5 * steps / el, "unit": "point-stage updates/s", "cores": all_cores,
+            "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"{steps} steps of the 128x64x64 stride-4 subsample of the 512x256x256 "
-                      f"stretched jet grid (FP64 C++ oracle, OpenMP), {el:.1f} s"}
+                      f"stretched jet grid (FP64 C++ oracle, -O3, OpenMP, {all_cores} threads), {el:.1f} s",
+            "one_thread": {"value": g.n * 5 * steps1 / el1, "cores": 1,
+                           "sample": f"{steps1} steps of the same subsample, {el1:.1f} s"},
+            "jet_box_64x48x48": {"value": gb.n * 5 * steps_b / el_b, "cores": all_cores,
+                                 "sample": f"{steps_b} steps of the 64x48x48 periodic jet box, {el_b:.2f} s"}}
 
 
 def fp32_error_vs_oracle():
@@ -97,7 +124,28 @@ def fp32_error_vs_oracle():
             "after_100_steps": dict(zip(names, rel(g100, o100)))}
 
 
-def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bool, stats_interval: int = 0):
+def _time_solver(s, n_adv: int, steps: int, warmup: int):
+    """Advance warmup steps, then time `steps` steps: wall clock around the
+    launches with the inputs resident, and hipEvents around each stage-kernel
+    launch.  Returns (value, ms_per_step, avg_launch_ms, bytes_per_launch)."""
+    import torch
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stage_ms, launches, stage_bytes = s.timing()
+    s.set_timing(False)
+    s.residual_norms()     # raises if the run went non-finite
+    return (n_adv * 5 * steps / el, el * 1e3 / steps, stage_ms / max(launches, 1),
+            stage_bytes / max(launches, 1))
+
+
+def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bool, stats_interval: int = 0,
+              with_secondary: bool = False):
     """fp64 / fp32: the periodic stretched jet block.  domain-fp64 /
     domain-fp32: the jet in a bounded 512 x 256 x 256 domain (uniform grid
     over x in [0, 4], y, z in [-1.5, 1.5]) with supersonic inflow at the jet
@@ -134,18 +182,24 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     else:
         s.set_grid_metrics(g.metrics)
     s.set_state(q)
+    value, ms_step, avg_ms, bytes_per_launch = _time_solver(s, n_adv, steps, warmup)
+    secondary = None
+    if with_secondary and form == "fp64":
+        # the FP32-flux form on the same resident workload, timed the same way
+        s32 = B.Solver(g.dims, B.params_default(re_d=1.0e6, precision=B.JZ_FP32_FLUX))
+        s32.set_grid_metrics(g.metrics)
+        s32.set_state(q)
+        v32, ms32, avg32, bytes32 = _time_solver(s32, n_adv, steps, warmup)
+        s32.close()
+        ach32 = bytes32 / (avg32 * 1e-3) / 1e9
+        secondary = {"form": "fp32", "value": v32, "unit": "point-stage updates/s", "ms_per_step": ms32,
+                     "speedup_vs_fp64": v32 / value,
+                     "dtype": "f32 (fluxes) + f64 (accumulation, J, norms)",
+                     "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": ach32 / HBM_PEAK_GBS, "traffic": _traffic("stage_fp32flux"),
+                                  "kernel": "stage_fp32flux", "avg_launch_ms": avg32,
+                                  "algorithmic_bytes_per_launch": bytes32}}
     del q
-    s.advance(warmup)
-    torch.cuda.synchronize()
-    s.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.advance(steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    stage_ms, launches, stage_bytes = s.timing()
-    s.set_timing(False)
-    s.residual_norms()     # raises if the run went non-finite
     stats_info = None
     if cylinder and stats_interval > 0:
         # the statistics of the run, and the potential core on the axis
@@ -158,15 +212,12 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
                       "potential_core_length": ST.potential_core_length(g.axes[0], axis_u, 1.4),
                       "max_rms_u": float(st["rms_u"].max())}
     s.close()
-    value = n_adv * 5 * steps / el
-    avg_ms = stage_ms / max(launches, 1)
-    bytes_per_launch = stage_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernel = "stage_fp64" if prec_name == "fp64" else "stage_fp32flux"
     traffic = None if (domain or cylinder) else _traffic(kernel)
     out = {
         "metric": "point-stage updates/s", "value": value, "unit": "point-stage updates/s",
-        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": el * 1e3 / steps,
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec_name == "fp64" else "f32 (fluxes) + f64 (accumulation, J, norms)",
         "data": "synthetic",
@@ -182,6 +233,8 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
     }
     if stats_info is not None:
         out["stats"] = stats_info
+    if secondary is not None:
+        out["secondary"] = secondary
     if with_error and form == "fp32":
         out["error_vs_oracle"] = fp32_error_vs_oracle()
     if with_cpu and not (domain or cylinder):
@@ -310,6 +363,8 @@ def main(argv=None):
     ap.add_argument("--serve-mode", default="streams", choices=["streams", "batch"],
                     help="serve forms: resident runs on their own streams, or one batch over them")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="fp64 form: skip the FP32-flux form timed on the same workload")
     ap.add_argument("--stats-interval", type=int, default=0,
                     help="cylinder forms: accumulate time-averaged statistics every this many steps")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -337,7 +392,8 @@ def main(argv=None):
         out = run_serve(a.form.split("-")[1], a.runs, not a.no_sequential, a.serve_mode)
     else:
         out = run_block(a.form, a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu),
-                        with_error=not a.no_error, stats_interval=a.stats_interval)
+                        with_error=not a.no_error, stats_interval=a.stats_interval,
+                        with_secondary=not a.no_secondary)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -9,5 +9,5 @@ binding) never touches it, and it never touches the product path.
 same residual used only to cross-check the C++ loops on tiny blocks.
 """
 from .core import (Params, default_params, metrics_tl, residual, fields, cfl_dt, step,  # noqa: F401
-                   advance, apply_bc, build, lib_path, BC_PERIODIC, BC_INFLOW, BC_FARFIELD)
+                   advance, apply_bc, build, lib_path, threads, BC_PERIODIC, BC_INFLOW, BC_FARFIELD)
 from . import core  # noqa: F401

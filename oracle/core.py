@@ -75,8 +75,10 @@ def _load():
         lib.jzo_cfl_dt.argtypes = [i, i, i, pp, dp, dp, dp, dp]
         lib.jzo_step.argtypes = [i, i, i, pp, dp, dp, ctypes.c_double, dp, dp, dp]
         lib.jzo_advance.argtypes = [i, i, i, pp, dp, dp, i, dp, dp, dp]
+        lib.jzo_threads.argtypes = [i]
         for f in (lib.jzo_params_default, lib.jzo_metrics_tl, lib.jzo_metrics_tl_bc, lib.jzo_apply_bc,
-                  lib.jzo_residual, lib.jzo_fields, lib.jzo_cfl_dt, lib.jzo_step, lib.jzo_advance):
+                  lib.jzo_residual, lib.jzo_fields, lib.jzo_cfl_dt, lib.jzo_step, lib.jzo_advance,
+                  lib.jzo_threads):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -189,6 +191,12 @@ def advance(dims, params: Params, m, q, nsteps: int):
     if rc:
         raise ValueError(f"jzo_advance failed ({rc})")
     return qn, t.value, rms, linf
+
+
+def threads(n: int = 0) -> int:
+    """Worker threads of the oracle's loops: n > 0 sets them; returns the
+    count in use."""
+    return int(_load().jzo_threads(int(n)))
 
 
 def apply_bc(dims, params: Params, m, q, q0) -> np.ndarray:

@@ -38,6 +38,9 @@
 // "parity unpinned" against the paper, which prints none.
 #include <cmath>
 #include <cstddef>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -674,6 +677,18 @@ int jzo_apply_bc(int ni, int nj, int nk, const jzo_params* P, const double* m, d
   Block b(ni, nj, nk, P->bc);
   apply_bc(b, *P, m, q, q0);
   return 0;
+}
+
+// Worker threads of the loops (for timing the oracle at a given core count):
+// n > 0 sets them; returns the count the next loop will use.
+int jzo_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 // nsteps steps; *t accumulates the simulated time.

@@ -34,7 +34,8 @@ hipError_t launch_stats_finalize(const double* acc, long long N, double inv_n, d
 hipError_t launch_stats_profile(const double* soa, long long N, int ni, int nj, int nk, int i, const int* bins,
                                 int nbins, double* out, hipStream_t st);
 hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
-                     const int n[3], const int bc[6], double gamma, double mach_inf, double* axis_mean, hipStream_t st);
+                     const int n[3], const int bc[6], double gamma, double mach_inf, double* axis_mean,
+                     const double* ref, hipStream_t st);
 hipError_t launch_metrics_tl(const double* X, const double* period9, int ni, int nj, int nk, int bnd, void* m, double* jac,
                              bool met32, hipStream_t st);
 hipError_t launch_check_met32(const float* m32, const double* jac, long long N, int axis_ni, int axis_nj, int* flag,
@@ -89,7 +90,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //              floats are the float stage states Q32a, Q32b) | metrics
 //              (9 floats per node) | J (1 double per node)
 struct Layout {
-  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, stats, axis, total;
+  size_t q0, stage, q32a, q32b, met, jac, norm_part, lam_part, clock, flag, stats, axis, ref, total;
   long long np;
 };
 
@@ -202,7 +203,7 @@ int partial_capacity(int ni, int nj, int nk, const Tiling& t) {
   return fine > t.nblocks ? fine : t.nblocks;
 }
 
-Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats, int axis_ni) {
+Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats, int axis_ni, long long ref_nodes) {
   Layout L;
   std::memset(&L, 0, sizeof L);
   size_t off = 0;
@@ -232,8 +233,19 @@ Layout layout_for(long long N, const Tiling& t, int prec, int cap, bool stats, i
   // centreline: the azimuthal mean of the five conserved variables at each
   // axial station (computed once per stage, read by every axis node)
   L.axis = axis_ni > 0 ? take((size_t)axis_ni * 5 * sizeof(double)) : 0;
+  // FP32-flux with physical faces: the double states of the far-field
+  // reference planes (see StageArgs::ref)
+  L.ref = ref_nodes > 0 ? take((size_t)ref_nodes * 5 * sizeof(double)) : 0;
   L.total = off;
   return L;
+}
+
+// nodes of the FP32-flux far-field reference buffer (0: none needed)
+long long ref_nodes_of(int ni, int nj, int nk, const jz_params* p) {
+  if (!p || p->precision != JZ_FP32_FLUX || !bounded_mask(p)) return 0;
+  const int n[3] = {ni, nj, nk};
+  long long off[3];
+  return ref_layout(n, bounded_mask(p), off);
 }
 
 bool params_ok(const jz_params* p, std::string* why) {
@@ -358,6 +370,7 @@ struct jz_solver {
   int* flag;
   double* stats;          // sums of u, u^2, p, p^2 per node, or NULL
   double* axis_mean;      // centreline: azimuthal means per axial station, or NULL
+  double* ref;            // FP32-flux far-field reference states, or NULL
   long long stat_samples; // samples in the sums
   long long stat_steps;   // steps since the last reset (samples every stats_interval)
   // timing: events recorded around stage launches (ev), and created ones
@@ -386,7 +399,8 @@ void setup_shape(jz_solver* s, int ni, int nj, int nk, const jz_params* p) {
   s->in = interior_of(ni, nj, nk, p);
   s->prec = p->precision;
   s->cap = partial_capacity(ni, nj, nk, s->tl);
-  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0, p->bc[2] == JZ_BC_AXIS ? ni : 0);
+  s->L = layout_for(s->N, s->tl, s->prec, s->cap, p->stats_interval > 0, p->bc[2] == JZ_BC_AXIS ? ni : 0,
+                    ref_nodes_of(ni, nj, nk, p));
   s->timing = false;
   s->stage_ms_acc = 0;
   s->stage_launches_acc = 0;
@@ -408,6 +422,7 @@ void bind_workspace(jz_solver* s) {
   s->flag = (int*)(s->ws + s->L.flag);
   s->stats = s->L.stats ? (double*)(s->ws + s->L.stats) : nullptr;
   s->axis_mean = s->L.axis ? (double*)(s->ws + s->L.axis) : nullptr;
+  s->ref = s->L.ref ? (double*)(s->ws + s->L.ref) : nullptr;
   s->stat_samples = 0;
   s->stat_steps = 0;
   s->grid_set = s->state_set = s->dt_valid = false;
@@ -454,7 +469,7 @@ size_t jz_workspace_bytes(int ni, int nj, int nk, const jz_params* p) {
   Tiling t;
   pick_tiling(ni, nj, nk, p, &t);
   return layout_for((long long)ni * nj * nk, t, p->precision, partial_capacity(ni, nj, nk, t), p->stats_interval > 0,
-                    p->bc[2] == JZ_BC_AXIS ? ni : 0)
+                    p->bc[2] == JZ_BC_AXIS ? ni : 0, ref_nodes_of(ni, nj, nk, p))
       .total;
 }
 
@@ -635,6 +650,9 @@ static StageArgs stage_args(jz_solver* s, const void* qin, void* qout, double al
   a.nchunks = s->tl.nchunks;
   a.in = s->in;
   a.ph = s->ph;
+  a.ref = nullptr;
+  const int n[3] = {s->ni, s->nj, s->nk};
+  ref_layout(n, s->in.bnd, a.ref_off);
   return a;
 }
 
@@ -749,6 +767,9 @@ static int advance_steps(jz_solver* s, int nsteps) {
       // overwrites nodes another one still reads as halo.
       void* out = (ns == 1) ? (void*)s->qa : last ? (void*)s->q0 : ((k % 2 == 0) ? bufA : bufB);
       StageArgs a = stage_args(s, in, out, s->p.rk_alpha[k]);
+      // a float stage state keeps the double states of its far-field reference planes
+      const bool float_out = s->prec == JZ_FP32_FLUX && !last && ns > 1;
+      if (float_out) a.ref = s->ref;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (s->timing) {
         int rc_ev = take_event_pair(s, &e0, &e1);
@@ -764,8 +785,8 @@ static int advance_steps(jz_solver* s, int nsteps) {
       }
       if (s->in.bnd) {
         const int n[3] = {s->ni, s->nj, s->nk};
-        HIP_TRY(launch_bc(out, s->prec == JZ_FP32_FLUX && !last, s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, n,
-                          s->p.bc, s->p.gamma, s->p.mach_inf, s->axis_mean, s->stream));
+        HIP_TRY(launch_bc(out, float_out, s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, n, s->p.bc, s->p.gamma,
+                          s->p.mach_inf, s->axis_mean, float_out ? s->ref : nullptr, s->stream));
       }
       if (ns == 1)
         HIP_TRY(hipMemcpyAsync(s->q0, s->qa, 5 * s->N * sizeof(double), hipMemcpyDeviceToDevice, s->stream));

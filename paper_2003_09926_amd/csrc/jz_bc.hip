@@ -19,6 +19,8 @@ struct BcArgs {
   double gamma;
   double mach_inf;       // free-stream velocity along x in ambient sound speeds
   long long count;       // 4 layers x n_e x n_f nodes
+  const double* ref;     // double states of the reference planes (float stage states), or NULL
+  long long ref_off;     // offset of direction d's two planes in ref (nodes)
 };
 
 // Far-field state from the one-dimensional characteristics normal to the face
@@ -158,7 +160,21 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
   cr[d] = lo ? 2 : b.n[d] - 3;
   const long long ref = cr[0] + (long long)b.n[0] * (cr[1] + (long long)b.n[1] * cr[2]);
   double qi[5], qb[5], nh[3];
-  for (int v = 0; v < 5; ++v) qi[v] = (double)q[5 * ref + v];
+  // the stage kernel kept double updates for the reference nodes it advanced;
+  // a reference node inside another direction's boundary layers (along the
+  // edges and corners of the block) has the value an earlier pass of this
+  // stage set, in the stage state itself
+  bool advanced = true;
+  for (int x = 0; x < 3; ++x)
+    if (x != d && b.bc[2 * x] != 0 && (cr[x] < 2 || cr[x] > b.n[x] - 3)) advanced = false;
+  if (b.ref && advanced) {
+    // a float stage state: the rule decides from the double update the stage
+    // kept for the reference plane, as for a double state
+    const long long o = b.ref_off + (lo ? 0 : 1) * (long long)b.n[e] * b.n[f] + cr[e] + (long long)b.n[e] * cr[f];
+    for (int v = 0; v < 5; ++v) qi[v] = b.ref[5 * o + v];
+  } else {
+    for (int v = 0; v < 5; ++v) qi[v] = (double)q[5 * ref + v];
+  }
   typename std::conditional<MET32, float, double>::type sm[9];
   double J;
   met.load(node, sm, J);
@@ -175,7 +191,13 @@ __global__ __launch_bounds__(256) void bc_kernel(T* __restrict__ q, const double
 
 template <typename T, bool MET32>
 hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double* jac, const int n[3],
-                           const int bc[6], double gamma, double mach_inf, double* axis_mean, hipStream_t st) {
+                           const int bc[6], double gamma, double mach_inf, double* axis_mean, const double* ref,
+                           hipStream_t st) {
+  long long ref_off[3];
+  int bnd = 0;
+  for (int d = 0; d < 3; ++d)
+    if (bc[2 * d] != 0) bnd |= 1 << d;
+  ref_layout(n, bnd, ref_off);
   MetView<MET32> mv;
   mv.m = (decltype(mv.m))met;
   mv.jac = jac;
@@ -188,6 +210,8 @@ hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double
     b.gamma = gamma;
     b.mach_inf = mach_inf;
     b.count = 4LL * n[(d + 1) % 3] * n[(d + 2) % 3];
+    b.ref = ref;
+    b.ref_off = ref_off[d];
     if (d == 1 && bc[2] == 3) {
       // the centreline means, from ring 2 as the xi pass left it
       if (!axis_mean) return hipErrorInvalidValue;
@@ -209,16 +233,19 @@ hipError_t launch_bc_typed(T* q, const double* q0, const void* met, const double
 
 // Boundary conditions on the stage state q (node-major; double, or float when
 // q_float), with inflow layers taken from Q(0) = q0.  axis_mean: scratch of
-// 5 x n[0] doubles, required when the eta- face is the centreline.  No-op for
-// a periodic block.
+// 5 x n[0] doubles, required when the eta- face is the centreline.  ref: for
+// a float stage state, the double states of the far-field reference planes
+// (ref_layout) the stage kept, from which the far-field rule then decides
+// (NULL: the rule reads q).  No-op for a periodic block.
 hipError_t launch_bc(void* q, bool q_float, const double* q0, const void* met, const double* jac, bool met32,
-                     const int n[3], const int bc[6], double gamma, double mach_inf, double* axis_mean, hipStream_t st) {
+                     const int n[3], const int bc[6], double gamma, double mach_inf, double* axis_mean,
+                     const double* ref, hipStream_t st) {
   if (q_float) {
-    if (met32) return launch_bc_typed<float, true>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
-    return launch_bc_typed<float, false>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
+    if (met32) return launch_bc_typed<float, true>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, ref, st);
+    return launch_bc_typed<float, false>((float*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, ref, st);
   }
-  if (met32) return launch_bc_typed<double, true>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
-  return launch_bc_typed<double, false>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, st);
+  if (met32) return launch_bc_typed<double, true>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, ref, st);
+  return launch_bc_typed<double, false>((double*)q, q0, met, jac, n, bc, gamma, mach_inf, axis_mean, ref, st);
 }
 
 }  // namespace jz

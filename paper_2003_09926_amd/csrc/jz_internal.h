@@ -76,6 +76,13 @@ struct StageArgs {
   int tiles_i, tiles_j, kchunk, nchunks;
   Interior in;          // tiles and chunks cover [lo, hi) of each direction
   Phys ph;
+  // FP32-flux intermediate stages of a block with physical faces: the double
+  // update of every node on a far-field reference plane (index 2 or n-3
+  // along a bounded direction d) also goes to ref + 5 * (ref_off[d] + side *
+  // n_e n_f + c_e + n_e c_f), (e, f) the other two directions in order, so
+  // that the boundary rule decides from the double state; NULL otherwise
+  double* ref;
+  long long ref_off[3];
 };
 
 // One member block of a batch: its device buffers, shape and physics.  The
@@ -98,6 +105,24 @@ struct BlockDesc {
   StepCtl ctl;
   Phys ph;
 };
+
+// The two directions of the faces normal to d, the faster first.
+__host__ __device__ inline int face_e(int d) { return d == 0 ? 1 : 0; }
+__host__ __device__ inline int face_f(int d) { return d == 2 ? 1 : 2; }
+
+// Offset (in nodes) of the reference planes of each bounded direction in the
+// FP32-flux reference buffer (-1 for a periodic direction), and the buffer's
+// total node count: two planes of n_e x n_f nodes per bounded direction.
+__host__ __device__ inline long long ref_layout(const int n[3], int bnd, long long off[3]) {
+  long long tot = 0;
+  for (int d = 0; d < 3; ++d) {
+    off[d] = -1;
+    if (!((bnd >> d) & 1)) continue;
+    off[d] = tot;
+    tot += 2LL * n[face_e(d)] * n[face_f(d)];
+  }
+  return tot;
+}
 
 __host__ __device__ inline int wrap_index(int i, int n) {
   int r = i % n;

@@ -10,6 +10,8 @@ namespace jz {
 
 // kind: 0 = first stage (double in, float out, norms)
 //       1 = middle stage (float in, float out)
+//       (with a.ref set, kinds 0 and 1 also keep the double updates of the
+//       far-field reference planes: blocks with physical faces)
 //       2 = last stage (float in, double out, next-dt lambda)
 //       3 = single stage (double in, double out, norms + lambda)
 //       4 = residual evaluation (double in, double R out)
@@ -17,8 +19,14 @@ template <int BX, int BY>
 static hipError_t launch_shape32(const StageArgs& a, const int* flag, int kind, int nblocks, hipStream_t st) {
   const dim3 grid(nblocks), block(stage_threads<float, BX, BY>());
   switch (kind) {
-    case 0: hipLaunchKernelGGL((stage_kernel<float, double, float, true, BX, BY, 1>), grid, block, 0, st, a, flag); break;
-    case 1: hipLaunchKernelGGL((stage_kernel<float, float, float, true, BX, BY, 0>), grid, block, 0, st, a, flag); break;
+    case 0:
+      if (a.ref) hipLaunchKernelGGL((stage_kernel<float, double, float, true, BX, BY, 9>), grid, block, 0, st, a, flag);
+      else hipLaunchKernelGGL((stage_kernel<float, double, float, true, BX, BY, 1>), grid, block, 0, st, a, flag);
+      break;
+    case 1:
+      if (a.ref) hipLaunchKernelGGL((stage_kernel<float, float, float, true, BX, BY, 8>), grid, block, 0, st, a, flag);
+      else hipLaunchKernelGGL((stage_kernel<float, float, float, true, BX, BY, 0>), grid, block, 0, st, a, flag);
+      break;
     case 2: hipLaunchKernelGGL((stage_kernel<float, float, double, true, BX, BY, 2>), grid, block, 0, st, a, flag); break;
     case 3: hipLaunchKernelGGL((stage_kernel<float, double, double, true, BX, BY, 3>), grid, block, 0, st, a, flag); break;
     case 4: hipLaunchKernelGGL((stage_kernel<float, double, double, true, BX, BY, 4>), grid, block, 0, st, a, flag); break;

@@ -245,6 +245,8 @@ constexpr int lds_pitch() {
 // MODE bit 0: accumulate norms of R (first stage)
 // MODE bit 1: max of sum_d lambda^d of the updated state (last stage -> next dt)
 // MODE bit 2: write R itself instead of the stage update
+// MODE bit 3: a float stage state of a block with far-field faces: keep the
+//             double update of the reference planes (StageArgs::ref)
 // One tile (logical index lt of the block described by A) through one stage.
 // Partial norms and lambda maxima go to slot lt, so the reductions do not
 // depend on how tiles are scheduled.  Every thread of the workgroup calls it;
@@ -262,6 +264,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   constexpr bool NORMS = (MODE & 1) != 0;
   constexpr bool LAMMAX = (MODE & 2) != 0;
   constexpr bool WRITE_R = (MODE & 4) != 0;
+  constexpr bool KEEP_REF = (MODE & 8) != 0 && std::is_same<TOut, float>::value && !PERSIST;
+  constexpr int BASE = MODE & 7;  // the stage kind without bit 3
   constexpr bool COMPACT = stage_compact<Rl, BX, BY>();
   static_assert(COMPACT ? NI + 2 * TI + 2 * TJ + 4 <= NT : TI * TJ + 4 * TI + 4 * TJ + 4 <= NT,
                 "tile roles exceed the workgroup");
@@ -273,7 +277,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   // stage keeps the ring: the FP32-flux first stage (norms at three waves
   // per SIMD) and, in the batch kernel, whose tile loop holds more
   // registers, every stage with reductions.
-  constexpr bool ZREG = MODE == 0 || (!PERSIST && (MODE == 2 || (MODE == 1 && sizeof(Rl) == 8)));
+  constexpr bool ZREG = BASE == 0 || (!PERSIST && (BASE == 2 || (BASE == 1 && sizeof(Rl) == 8)));
   constexpr int NPR = ZREG ? 1 : 3;
   // plane buffers (structure of arrays, one slot per tile column, rows of P)
   __shared__ Rl sPr[NPR][5][NS];   // u, v, w, T, p: the gradient plane, or a ring of three planes
@@ -304,7 +308,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       (19LL + 5 * NQB + 2 * NHV) * NS * (long long)sizeof(Rl) + 2LL * NI * (9 * (long long)sizeof(MT) + 8) + 256;
   constexpr long long REG_WAVES = (sizeof(Rl) == 4 ? 3 : 2) * 4 * 64;
   constexpr long long REG_WG = REG_WAVES / NT > 0 ? REG_WAVES / NT : 1;
-  constexpr bool MET_LDS = MODE == 2 && ZREG && !PERSIST && MET_LDS_WG * REG_WG <= 160LL * 1024;
+  constexpr bool MET_LDS = BASE == 2 && ZREG && !PERSIST && MET_LDS_WG * REG_WG <= 160LL * 1024;
   __shared__ MT sMo[MET_LDS ? 2 : 1][MET_LDS ? 9 : 1][MET_LDS ? NI : 1];
   __shared__ double sMoJ[MET_LDS ? 2 : 1][MET_LDS ? NI : 1];
   // Compact form: Q of the next gradient plane of each edge thread's
@@ -635,7 +639,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
         sFy[v][c] = F[1][v];
         Fzg[v] = F[2][v];
       }
-      if constexpr (COMPACT && MODE == 0) {
+      if constexpr (COMPACT && BASE == 0) {
         if (upd) update_loads();
       }
       // spectral radii and anisotropic dissipation scales
@@ -687,7 +691,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
     const bool own = isI && s >= kbeg - 1;  // plane kbeg-1 is not written
     Rl Hp[5] = {0, 0, 0, 0, 0};
     if (own) {
-      if constexpr (!(COMPACT && MODE == 0)) {
+      if constexpr (!(COMPACT && BASE == 0)) {
         if (upd) update_loads();
       }
       const Rl e2 = k2 * fmax(nus, nug);
@@ -785,6 +789,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
           }
 #pragma unroll
           for (int v = 0; v < 5; ++v) qout[5 * ns + v] = (TOut)qn[v];
+          if constexpr (KEEP_REF) {
+            // a node on a far-field reference plane also keeps its double
+            // update (see StageArgs::ref)
+            {
+              const int ci[3] = {ui, uj, s};
+              const int nn[3] = {A.ni, A.nj, A.nk};
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                if (A.ref_off[d] < 0) continue;
+                const int e = face_e(d), f = face_f(d);
+                const long long face = (long long)nn[e] * nn[f], at = ci[e] + (long long)nn[e] * ci[f];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                  if (ci[d] != (side ? nn[d] - 3 : 2)) continue;
+                  double* dst = A.ref + 5 * (A.ref_off[d] + side * face + at);
+#pragma unroll
+                  for (int v = 0; v < 5; ++v) dst[v] = qn[v];
+                }
+              }
+            }
+          }
           if (LAMMAX) {
             if (MET_LDS) {
 #pragma unroll
@@ -886,7 +911,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 // compiler (their 512 threads put two waves on every SIMD).
 template <typename Rl, int BX, int BY, int MODE>
 constexpr int stage_waves_per_eu() {
-  return (sizeof(Rl) == 4 && MODE != 3) ? 3 : stage_compact<Rl, BX, BY>() ? 2 : 1;
+  return (sizeof(Rl) == 4 && (MODE & 7) != 3) ? 3 : stage_compact<Rl, BX, BY>() ? 2 : 1;
 }
 
 // Single block: one workgroup per tile, tiles spread XCD by XCD.

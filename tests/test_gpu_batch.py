@@ -5,7 +5,10 @@ precision forms; a member that fails is frozen without disturbing the rest."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2003_09926_amd import inputs as I
+
+from _parity import per_var_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +62,29 @@ def test_batch_members_bitwise_equal_alone(B, prec, tile):
         r2, l2 = s.residual_norms()
         assert np.array_equal(r2, rms) and np.array_equal(l2, linf)
         assert s.clock() == clk
+        s.close()
+
+
+@pytest.mark.parametrize("prec,tile", [(0, (0, 0)), (0, (16, 16)), (1, (0, 0))])
+def test_batch_members_match_oracle(B, prec, tile):
+    """Every member of a batch (own size, Mach and Re) against the oracle
+    advanced alone from the same state: FP64 within the 1e-12 state and 1e-9
+    increment bars after three steps, FP32-flux within its 1e-5 target.  The
+    default tile shapes (compact 16 x 12 in FP64) and the 16 x 16 shape."""
+    print(f"[gpu-case] batch vs oracle precision={prec} tile={tile}", flush=True)
+    cases = _cases()
+    ms = _members(B, cases, prec, tile)
+    with B.Batch(ms) as b:
+        b.advance(3)
+        b.synchronize()
+    for s, (g, q, kw) in zip(ms, cases):
+        qo, _, _, _ = oracle.advance(g.dims, oracle.default_params(**kw), g.metrics, q, 3)
+        qg = s.get_state()
+        if prec == 0:
+            assert max(per_var_rel(qg, qo)) <= 1e-12, g.dims
+            assert max(per_var_rel(qg - q, qo - q)) <= 1e-9, g.dims
+        else:
+            assert max(per_var_rel(qg, qo)) <= 1e-5, g.dims
         s.close()
 
 

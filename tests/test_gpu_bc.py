@@ -153,35 +153,85 @@ def test_bounded_tl_metrics_and_uniform_stream(B):
     np.testing.assert_allclose(q3, q, rtol=0, atol=1e-12)
 
 
+def _farfield_branches(q, m, dims, bc, gamma=1.4):
+    """Per far-field boundary node, the side the far-field rule takes entropy
+    and tangential velocity from, computed from the state of its reference
+    node (index 2 or n-3 along the face normal) as the rule defines it:
+    +-2 supersonic out/in, +1 subsonic outflow (interior), -1 subsonic inflow
+    (free stream).  Test-side restatement of the decision only."""
+    ni, nj, nk = dims
+    Q = q.reshape(5, nk, nj, ni)
+    M = m.reshape(10, nk, nj, ni)
+    out = []
+    for d in range(3):
+        for side in (0, 1):
+            if bc[2 * d + side] != I.BC_FARFIELD:
+                continue
+            n = dims[d]
+            ref = 2 if side == 0 else n - 3
+            for layer in ((0, 1) if side == 0 else (n - 2, n - 1)):
+                sl = [slice(None)] * 3
+                sl[2 - d] = ref
+                qi = Q[(slice(None),) + tuple(sl)]
+                sl[2 - d] = layer
+                mm = M[(slice(None),) + tuple(sl)]
+                r = qi[0]
+                u = qi[1:4] / r
+                p = (gamma - 1) * (qi[4] - 0.5 * r * (u ** 2).sum(0))
+                a = np.sqrt(gamma * p / r)
+                nh = np.stack([mm[9] * mm[3 * d + k] for k in range(3)])
+                nh = nh / np.sqrt((nh ** 2).sum(0))
+                if side == 0:
+                    nh = -nh
+                un = (u * nh).sum(0)
+                unb = 0.5 * (un + 2 * a / (gamma - 1) - 2 / (gamma - 1))   # free stream at rest, a = 1
+                out.append(np.where(un >= a, 2, np.where(un <= -a, -2, np.where(unb > 0, 1, -1))).ravel())
+    return np.concatenate(out)
+
+
 def test_bounded_fp32_flux_form_close_to_oracle(B):
-    """The FP32-flux form on the bounded jet domain stays as close to the FP64
-    oracle as it does on the periodic block of the same grid and state, after
-    1 and 20 steps.  The far-field rule switches the side that supplies
-    entropy and tangential velocity where u_n changes sign, and the form
-    takes that decision on float stage states; the state here keeps the flow
-    next to the faces free of tangential velocity and entropy differences (the
-    noise is confined to the supersonic core, r < 0.45), so that the switch is
-    continuous and both sides agree whichever way a near-zero u_n rounds."""
-    _log("bounded jet domain 40x30x26 FP32-flux vs periodic, 1 and 20 steps")
+    """The FP32-flux form on the bounded jet domain with the bench's own state
+    (noise on every node, up to the far-field faces, where the ambient fluid
+    is at rest and u_n is pure noise), against the FP64 oracle after 1, 20 and
+    100 steps, per conserved variable.  The far-field rule takes entropy and
+    tangential velocity from the interior or the free stream depending on the
+    sign of u_n, a jump of the size of the noise; it decides from the double
+    update of its reference node, which the FP32-flux stages keep for the
+    reference planes, so that it flips against the oracle only where u_n is
+    within the flux error (about 1e-8 relative) of 0.  The errors then stay
+    at the level of the same state on a periodic block (below 3 times it, or
+    1e-6 above it), the branches agree with the oracle's at the checked
+    steps, and the 100-step error meets the form's 1e-5 target.  (Deciding
+    from the float stage state instead flipped at a few nodes per step and
+    gave 1e-4 in rho v after one step.)"""
+    _log("bounded jet domain 40x30x26 FP32-flux vs periodic, 1, 20, 100 steps")
     c = CASES["jetdomain_40x30x26"]
-    g, q, bc = I.jet_domain_case(c["dims"], seed=4, bc=c["bc"], noise_radius=0.45)
+    g, q, bc = I.jet_domain_case(c["dims"], seed=4, bc=c["bc"])
     errs = {}
     for name, bcs in (("bounded", bc), ("periodic", (PER,) * 6)):
         P = oracle.default_params(bc=bcs)
-        q1, _, _, _ = oracle.step(g.dims, P, g.metrics, q)
-        q20, _, _, _ = oracle.advance(g.dims, P, g.metrics, q, 20)
+        ref, got = [], []
+        qo = q.copy()
         with B.Solver(g.dims, B.params_default(bc=bcs, precision=B.JZ_FP32_FLUX)) as s:
             s.set_grid_metrics(g.metrics)
             s.set_state(q)
-            s.advance(1)
-            g1 = s.get_state()
-            s.advance(19)
-            g20 = s.get_state()
-        errs[name] = (max(per_var_rel(g1, q1)), max(per_var_rel(g20, q20)))
-    print("[gpu-case] fp32 errors", errs, flush=True)
-    (b1, b20), (p1, p20) = errs["bounded"], errs["periodic"]
-    assert b1 <= 3.0 * p1 + 1e-6 and b20 <= 3.0 * p20 + 1e-5
-    assert b20 <= 1e-3
+            done = 0
+            for n in (1, 20, 100):
+                qo, _, _, _ = oracle.advance(g.dims, P, g.metrics, qo, n - done)
+                s.advance(n - done)
+                done = n
+                ref.append(qo)
+                got.append(s.get_state())
+        errs[name] = [per_var_rel(a, b) for a, b in zip(got, ref)]
+        if name == "bounded":
+            for a, b in zip(got, ref):
+                assert np.array_equal(_farfield_branches(a, g.metrics, g.dims, bc),
+                                      _farfield_branches(b, g.metrics, g.dims, bc))
+    print("[gpu-case] fp32 bounded / periodic errors per variable", errs, flush=True)
+    for eb, ep in zip(errs["bounded"], errs["periodic"]):
+        for v in range(5):
+            assert eb[v] <= 3.0 * ep[v] + 1e-6, (v, eb, ep)
+    assert max(errs["bounded"][2]) <= 1e-5
 
 
 def test_batch_rejects_bounded_members(B):
@@ -266,34 +316,35 @@ def test_cylinder_axis_many_azimuths(B):
         q32 = s.get_state()
     axis = q32.reshape(5, nk, nj, ni)[:, :, 0, 2:]
     assert np.all(axis == axis[:, :1, :])
-    d = q32 - qe
-    mom = np.linalg.norm(qe[1:4])
-    errs = [np.linalg.norm(d[0]) / np.linalg.norm(qe[0])] + [np.linalg.norm(d[v]) / mom for v in (1, 2, 3)] + \
-        [np.linalg.norm(d[4]) / np.linalg.norm(qe[4])]
-    assert max(errs) <= 1e-5
+    assert max(per_var_rel(q32, qe)) <= 1e-5
 
 
 def test_cylinder_fp32_flux_form_close_to_oracle(B):
-    """FP32-flux form on the cylindrical mesh after 5 steps.  The transverse
-    momenta are small next to the axial one (noise only in the core), so the
-    momentum errors are measured against the whole momentum vector; density
-    and energy against their own norms."""
-    _log("cylinder 40x16x24 FP32-flux, 5 steps")
+    """FP32-flux form on the cylindrical mesh with the bench's own state (noise
+    on every node), per conserved variable, after 1, 20 and 100 steps: within
+    the form's 1e-5 target at every checkpoint, and the far-field branches of
+    the outflow and lateral faces agree with the oracle's."""
+    _log("cylinder 40x16x24 FP32-flux, 1, 20, 100 steps")
     dims = (40, 16, 24)
-    g, q, bc = I.jet_cylinder_case(dims, seed=8, noise_radius=0.45)
+    g, q, bc = I.jet_cylinder_case(dims, seed=8)
     P = oracle.default_params(bc=bc)
-    q5, _, _, _ = oracle.advance(dims, P, g.metrics, q, 5)
+    qo = q.copy()
+    errs = []
     with B.Solver(dims, B.params_default(bc=bc, precision=B.JZ_FP32_FLUX)) as s:
         s.set_grid_metrics(g.metrics)
         s.set_state(q)
-        s.advance(5)
-        g5 = s.get_state()
-    d = g5 - q5
-    mom = np.linalg.norm(q5[1:4])
-    errs = [np.linalg.norm(d[0]) / np.linalg.norm(q5[0])] + [np.linalg.norm(d[v]) / mom for v in (1, 2, 3)] + \
-        [np.linalg.norm(d[4]) / np.linalg.norm(q5[4])]
-    print("[gpu-case] fp32 cylinder errors", per_var_rel(g5, q5), errs, flush=True)
-    assert max(errs) <= 1e-5
+        done = 0
+        for n in (1, 20, 100):
+            qo, _, _, _ = oracle.advance(dims, P, g.metrics, qo, n - done)
+            s.advance(n - done)
+            done = n
+            qg = s.get_state()
+            errs.append(per_var_rel(qg, qo))
+            fin = np.isfinite(g.metrics[9])
+            m = np.where(fin, g.metrics, 1.0)
+            assert np.array_equal(_farfield_branches(qg, m, dims, bc), _farfield_branches(qo, m, dims, bc))
+    print("[gpu-case] fp32 cylinder errors per variable", errs, flush=True)
+    assert max(max(e) for e in errs) <= 1e-5
 
 
 def test_axis_face_rules_are_validated(B):

@@ -1,10 +1,14 @@
 """Served form: continuous batching of arriving jet runs.  Every result must
-be bitwise the run computed alone (FP64), the HBM budget must hold, and runs
+be bitwise the run computed alone and within the oracle's bars (FP64 1e-12,
+FP32-flux 1e-5 relative L2 per variable), the HBM budget must hold, and runs
 must actually overlap on the device."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2003_09926_amd import inputs as I
+
+from _parity import per_var_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +44,11 @@ def test_served_results_equal_alone_and_budget_holds(prec, mode):
         _, alone = S.run_alone(S.Run(r.rid, r.arrival, r.dims, r.mach, r.re_d, r.steps, r.seed), prec, tile,
                                keep_result=True)
         assert np.array_equal(alone, r.result), r.rid
+        # and the oracle, advanced alone from the same jet box
+        g, q = I.jet_box_case(r.dims, mach=r.mach, seed=r.seed)
+        qo, _, _, _ = oracle.advance(r.dims, oracle.default_params(mach_j=r.mach, re_d=r.re_d), g.metrics, q,
+                                     r.steps)
+        assert max(per_var_rel(r.result, qo)) <= (1e-12 if prec == 0 else 1e-5), r.rid
     s = st.summary()
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
 
