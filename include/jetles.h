@@ -266,6 +266,40 @@ int jz_batch_get_timing(jz_batch* b, double* step_ms, long long* steps, long lon
 int jz_batch_synchronize(jz_batch* b);
 int jz_batch_destroy(jz_batch* b);
 
+/* ---- domains: one block split into padded sub-blocks ------------------
+ * The one-device part of the paper's domain decomposition (Sec. 4.1, the
+ * 2-D partitioning of Fig. comm_2d and its balancing rule; Sec. 4.3, the
+ * two-layer ghost fringe of Fig. ghost).  A periodic ni x nj x nk block is
+ * split into parts_i parts along xi and parts_k along zeta (eta whole);
+ * the part sizes along a direction differ by at most one node, the larger
+ * parts first.  Each part is a solver of its own with two ghost layers at
+ * both ends of each split direction, which it reads but does not advance;
+ * after every RK stage halo-copy kernels refill them from the neighbouring
+ * parts' stage results (periodic wrap between the first and last part),
+ * first along xi over all zeta layers, then along zeta over the whole
+ * padded xi width, which carries the corners.  dt is the CFL rule over all
+ * parts, the norms are summed over all parts, and the states are bitwise
+ * those of the unsplit block advanced with jz_advance.
+ *   p:    all six faces JZ_BC_PERIODIC, stats_interval 0, n_stages >= 2;
+ *   parts_i, parts_k >= 1, every part at least 2 nodes long;
+ *   hip_stream: all work is ordered on it (NULL = null stream).
+ * set_grid_metrics / set_state take the whole block's host arrays in the
+ * jz_set_grid_metrics / jz_set_state layouts (10 x N and 5 x N doubles);
+ * get_state writes the whole block's 5 x N host array.  get_clock and
+ * get_residual_norms report the common clock and the whole block's norms.
+ * Error codes as for the solver calls (JZ_EINVAL for bad sizes or
+ * parameters, JZ_ESTATE before the grid and state are set). */
+typedef struct jz_domain jz_domain;
+int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, int parts_k, void* hip_stream,
+                     jz_domain** out);
+int jz_domain_set_grid_metrics(jz_domain* d, const double* m);
+int jz_domain_set_state(jz_domain* d, const double* q);
+int jz_domain_advance(jz_domain* d, int nsteps);
+int jz_domain_get_state(jz_domain* d, double* q);
+int jz_domain_get_clock(jz_domain* d, double* t, double* next_dt, long long* steps);
+int jz_domain_get_residual_norms(jz_domain* d, double rms[5], double linf[5]);
+int jz_domain_destroy(jz_domain* d);
+
 /* ---- steps without device allocation -----------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.

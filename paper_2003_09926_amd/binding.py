@@ -97,6 +97,14 @@ def library() -> ctypes.CDLL:
         "jz_batch_synchronize": ([S], i),
         "jz_batch_destroy": ([S], i),
         "jz_advance_static": ([i, i, i, P, dp, dp, dp, i, ctypes.c_void_p], i),
+        "jz_domain_create": ([i, i, i, P, i, i, ctypes.c_void_p, ctypes.POINTER(S)], i),
+        "jz_domain_set_grid_metrics": ([S, dp], i),
+        "jz_domain_set_state": ([S, dp], i),
+        "jz_domain_advance": ([S, i], i),
+        "jz_domain_get_state": ([S, dp], i),
+        "jz_domain_get_clock": ([S, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(ll)], i),
+        "jz_domain_get_residual_norms": ([S, dp, dp], i),
+        "jz_domain_destroy": ([S], i),
         "jz_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -385,6 +393,69 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             library().jz_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Domain:
+    """A periodic block split into parts_i x parts_k padded sub-blocks whose
+    two-layer ghost fringes are refilled by halo copies after every stage;
+    the whole-block arrays go in and come out in the Solver layouts (host)."""
+
+    def __init__(self, dims, params: Optional[Params] = None, parts=(1, 1), stream=None):
+        import torch
+        self.dims = tuple(int(x) for x in dims)
+        self.n = self.dims[0] * self.dims[1] * self.dims[2]
+        self.params = params if params is not None else params_default()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(library().jz_domain_create(*self.dims, ctypes.byref(self.params), int(parts[0]), int(parts[1]),
+                                          ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h)),
+               "jz_domain_create")
+        self._h = h
+
+    def set_grid_metrics(self, m):
+        m = _as_host(m)
+        _check(library().jz_domain_set_grid_metrics(self._h, _host_ptr(m)), "jz_domain_set_grid_metrics")
+
+    def set_state(self, q):
+        q = _as_host(q)
+        _check(library().jz_domain_set_state(self._h, _host_ptr(q)), "jz_domain_set_state")
+
+    def advance(self, nsteps: int):
+        _check(library().jz_domain_advance(self._h, int(nsteps)), "jz_domain_advance")
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty((5, self.n))
+        _check(library().jz_domain_get_state(self._h, _host_ptr(out)), "jz_domain_get_state")
+        return out
+
+    def clock(self):
+        t, dt, st = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+        _check(library().jz_domain_get_clock(self._h, ctypes.byref(t), ctypes.byref(dt), ctypes.byref(st)),
+               "jz_domain_get_clock")
+        return t.value, dt.value, st.value
+
+    def residual_norms(self):
+        rms, linf = np.empty(5), np.empty(5)
+        _check(library().jz_domain_get_residual_norms(self._h, _host_ptr(rms), _host_ptr(linf)),
+               "jz_domain_get_residual_norms")
+        return rms, linf
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().jz_domain_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -52,6 +52,10 @@ hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCt
 hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
                                 int* flag, hipStream_t st);
 hipError_t launch_reset_clock(Clock* clk, int* flag, hipStream_t st);
+hipError_t launch_halo_copy(void* dst, const void* src, bool is_float, int d, const int nd[3], const int nsrc[3],
+                            int dl0, int sl0, hipStream_t st);
+hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st);
+hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st);
 hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, hipStream_t st);
 }  // namespace jz
 
@@ -120,7 +124,9 @@ long long interior_count(const Interior& in) {
   return (long long)(in.hi[0] - in.lo[0]) * (in.hi[1] - in.lo[1]) * (in.hi[2] - in.lo[2]);
 }
 
-void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
+// `over`: the nodes to tile when they are not the parameters' own interior
+// (the sub-blocks of a domain, whose ghost layers are not advanced)
+void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t, const Interior* over = nullptr) {
   const bool f32 = p && p->precision == JZ_FP32_FLUX;
   // defaults measured on the 512 x 256 x 256 workload: tile rows of 16 or 32
   // owned columns (whole 16-lane groups, so a row's LDS reads meet no bank
@@ -136,7 +142,7 @@ void pick_tiling(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
   t->ti = t->bx - 4;
   t->tj = t->by - 4;
   // tiles and chunks cover the advanced nodes only
-  const Interior in = interior_of(ni, nj, nk, p);
+  const Interior in = over ? *over : interior_of(ni, nj, nk, p);
   const int ei = in.hi[0] - in.lo[0], ej = in.hi[1] - in.lo[1], ek = in.hi[2] - in.lo[2];
   t->tiles_i = (ei + t->ti - 1) / t->ti;
   t->tiles_j = (ej + t->tj - 1) / t->tj;
@@ -174,8 +180,8 @@ int auto_kchunk(int tiles, int nk, long long slots) {
 
 // pick_tiling, then (kchunk left to the library) the chunk length for the
 // current device's CU count and the shape's occupancy
-void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* t) {
-  pick_tiling(ni, nj, nk, p, t);
+void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* t, const Interior* over = nullptr) {
+  pick_tiling(ni, nj, nk, p, t, over);
   if (p && p->kchunk > 0) return;
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
@@ -183,7 +189,7 @@ void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* 
   const int per_cu = (p && p->precision == JZ_FP32_FLUX) ? stage_wg_per_cu_fp32(t->bx, t->by)
                                                           : stage_wg_per_cu_fp64(t->bx, t->by);
   if (per_cu < 1 || ncu < 1) return;
-  const Interior in = interior_of(ni, nj, nk, p);
+  const Interior in = over ? *over : interior_of(ni, nj, nk, p);
   const int ek = in.hi[2] - in.lo[2];
   // The compact FP64 shape (16 x 12 tiles, two workgroups per CU) runs its
   // workgroups unsynchronised, so the rounds model does not hold for it;
@@ -1528,6 +1534,298 @@ int jz_batch_destroy(jz_batch* b) {
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->st) (void)hipStreamDestroy(b->st);
   delete b;
+  return JZ_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// domains: one periodic block split into sub-blocks along xi and zeta, each
+// padded with two ghost layers along its split directions that halo copies
+// refill after every stage (the paper's decomposition, Sec. 4.1, and its
+// two-layer ghost exchange, Sec. 4.3, on one device)
+// ===========================================================================
+struct jz_domain {
+  int n[3];
+  int parts[3];                  // sub-blocks per direction (parts[1] = 1)
+  std::vector<int> off[3], len[3];  // per direction: first node and node count of each part
+  std::vector<jz_solver*> sub;   // part (a, c) (xi index a, zeta index c) at a + parts[0] * c
+  jz_params p;
+  hipStream_t stream;
+  DomainSub* d_sub;              // device table for the group reductions
+  int halo;                      // bit d: direction d is split
+  long long n_interior;
+  bool dt_valid;
+};
+
+namespace {
+
+int dom_index(const jz_domain* D, int a, int c) { return a + D->parts[0] * c; }
+
+// padded extent of part a along d
+int dom_pad(const jz_domain* D, int d, int a) { return D->len[d][a] + ((D->halo >> d) & 1 ? 4 : 0); }
+
+// Copy the padded region of part (a, c) out of a whole-block SoA host array
+// of `rows` rows (periodic wrap), or back into it (interior nodes only).
+void dom_extract(const jz_domain* D, int a, int c, const double* whole, int rows, std::vector<double>& out) {
+  const int sn[3] = {dom_pad(D, 0, a), D->n[1], dom_pad(D, 2, c)};
+  const int o[3] = {D->off[0][a] - ((D->halo & 1) ? 2 : 0), 0, D->off[2][c] - ((D->halo & 4) ? 2 : 0)};
+  const long long N = (long long)D->n[0] * D->n[1] * D->n[2], sN = (long long)sn[0] * sn[1] * sn[2];
+  out.assign((size_t)rows * sN, 0.0);
+  for (int k = 0; k < sn[2]; ++k)
+    for (int j = 0; j < sn[1]; ++j)
+      for (int i = 0; i < sn[0]; ++i) {
+        const long long g = wrap_index(o[0] + i, D->n[0]) +
+                            (long long)D->n[0] * (j + (long long)D->n[1] * wrap_index(o[2] + k, D->n[2]));
+        const long long l = i + (long long)sn[0] * (j + (long long)sn[1] * k);
+        for (int r = 0; r < rows; ++r) out[r * sN + l] = whole[r * N + g];
+      }
+}
+
+void dom_insert(const jz_domain* D, int a, int c, const std::vector<double>& part, double* whole) {
+  const int sn[3] = {dom_pad(D, 0, a), D->n[1], dom_pad(D, 2, c)};
+  const int g0[3] = {(D->halo & 1) ? 2 : 0, 0, (D->halo & 4) ? 2 : 0};
+  const long long N = (long long)D->n[0] * D->n[1] * D->n[2], sN = (long long)sn[0] * sn[1] * sn[2];
+  for (int k = 0; k < D->len[2][c]; ++k)
+    for (int j = 0; j < D->n[1]; ++j)
+      for (int i = 0; i < D->len[0][a]; ++i) {
+        const long long g = (D->off[0][a] + i) + (long long)D->n[0] * (j + (long long)D->n[1] * (D->off[2][c] + k));
+        const long long l = (g0[0] + i) + (long long)sn[0] * (j + (long long)sn[1] * (g0[2] + k));
+        for (int r = 0; r < 5; ++r) whole[r * N + g] = part[r * sN + l];
+      }
+}
+
+// The stage output buffer of stage k (as jz_advance rotates them).
+void* dom_stage_out(jz_solver* s, int k, int ns) {
+  if (k == ns - 1) return s->q0;
+  const bool f32 = s->prec == JZ_FP32_FLUX;
+  return (k % 2 == 0) ? (f32 ? (void*)s->q32a : (void*)s->qa) : (f32 ? (void*)s->q32b : (void*)s->qb);
+}
+
+// Refill the ghost layers of every part's buffer of stage k: first along xi
+// (all zeta planes), then along zeta over the whole padded width, which
+// carries the xi ghost columns -- and with them the corners -- across.
+int dom_exchange(jz_domain* D, int k, int ns) {
+  const bool f32 = D->p.precision == JZ_FP32_FLUX && k != ns - 1;
+  for (int d = 0; d < 3; d += 2) {
+    if (!((D->halo >> d) & 1)) continue;
+    for (int c = 0; c < D->parts[2]; ++c)
+      for (int a = 0; a < D->parts[0]; ++a) {
+        jz_solver* dst = D->sub[dom_index(D, a, c)];
+        // the neighbouring parts along d (periodic: the first and last are neighbours)
+        const int np = D->parts[d], pos = d == 0 ? a : c;
+        const int prev = (pos + np - 1) % np, next = (pos + 1) % np;
+        jz_solver* lo = D->sub[d == 0 ? dom_index(D, prev, c) : dom_index(D, a, prev)];
+        jz_solver* hi = D->sub[d == 0 ? dom_index(D, next, c) : dom_index(D, a, next)];
+        const int nd[3] = {dst->ni, dst->nj, dst->nk};
+        const int nl[3] = {lo->ni, lo->nj, lo->nk}, nh[3] = {hi->ni, hi->nj, hi->nk};
+        // ghost layers 0, 1 <- the last two interior layers of the lower neighbour;
+        // n-2, n-1 <- its upper neighbour's first two
+        HIP_TRY(launch_halo_copy(dom_stage_out(dst, k, ns), dom_stage_out(lo, k, ns), f32, d, nd, nl, 0,
+                                 nl[d] - 4, D->stream));
+        HIP_TRY(launch_halo_copy(dom_stage_out(dst, k, ns), dom_stage_out(hi, k, ns), f32, d, nd, nh, nd[d] - 2,
+                                 2, D->stream));
+      }
+  }
+  return JZ_OK;
+}
+
+int dom_upload_table(jz_domain* D) {
+  std::vector<DomainSub> t(D->sub.size());
+  for (size_t i = 0; i < D->sub.size(); ++i) {
+    jz_solver* s = D->sub[i];
+    t[i].clock = s->clock;
+    t[i].norm_part = s->norm_part;
+    t[i].lam_part = s->lam_part;
+    t[i].flag = s->flag;
+    t[i].nb_tiles = s->tl.nblocks;
+    t[i].nb_lmax = lambda_max_blocks(s->N);
+  }
+  HIP_TRY(hipMemcpyAsync(D->d_sub, t.data(), t.size() * sizeof(DomainSub), hipMemcpyHostToDevice, D->stream));
+  HIP_TRY(hipStreamSynchronize(D->stream));
+  return JZ_OK;
+}
+
+StepCtl dom_ctl(const jz_domain* D) {
+  StepCtl c;
+  c.cfl = D->p.cfl;
+  c.dt_fixed = D->p.dt_fixed;
+  c.inv_n = 1.0 / (double)D->n_interior;
+  return c;
+}
+
+int dom_ensure_dt(jz_domain* D) {
+  if (D->dt_valid) return JZ_OK;
+  for (jz_solver* s : D->sub) {
+    const int n[3] = {s->ni, s->nj, s->nk};
+    HIP_TRY(launch_lambda_max(s->q0, s->met, s->jac, s->prec == JZ_FP32_FLUX, s->N, n, s->in, s->p.gamma,
+                              s->lam_part, D->stream));
+  }
+  HIP_TRY(launch_domain_dt(D->d_sub, (int)D->sub.size(), dom_ctl(D), D->stream));
+  // the parts' clocks hold the common dt now (their own getters must not replace it)
+  for (jz_solver* s : D->sub) s->dt_valid = true;
+  D->dt_valid = true;
+  return JZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, int parts_k, void* hip_stream,
+                     jz_domain** out) {
+  if (!out) return fail(JZ_EINVAL, "jz_domain_create: out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!params_ok(p, &why)) return fail(JZ_EINVAL, "jz_domain_create: %s", why.c_str());
+  if (bounded_mask(p) || p->stats_interval > 0 || p->n_stages < 2)
+    return fail(JZ_EINVAL, "jz_domain_create: domains take periodic blocks without statistics and with n_stages >= 2");
+  if (parts_i < 1 || parts_k < 1 || ni < 2 * parts_i || nk < 2 * parts_k || nj < 1)
+    return fail(JZ_EINVAL, "jz_domain_create: every part needs at least 2 nodes along a split direction");
+  if ((long long)ni * nj * nk > (1LL << 36)) return fail(JZ_EINVAL, "jz_domain_create: block too large");
+  jz_domain* D = new jz_domain();
+  D->n[0] = ni;
+  D->n[1] = nj;
+  D->n[2] = nk;
+  D->parts[0] = parts_i;
+  D->parts[1] = 1;
+  D->parts[2] = parts_k;
+  D->halo = (parts_i > 1 ? 1 : 0) | (parts_k > 1 ? 4 : 0);
+  D->p = *p;
+  D->stream = (hipStream_t)hip_stream;
+  D->d_sub = nullptr;
+  D->n_interior = (long long)ni * nj * nk;
+  D->dt_valid = false;
+  // balanced parts: sizes differ by at most one node, larger ones first
+  for (int d = 0; d < 3; ++d) {
+    const int np = D->parts[d];
+    int o = 0;
+    for (int a = 0; a < np; ++a) {
+      const int l = D->n[d] / np + (a < D->n[d] % np ? 1 : 0);
+      D->off[d].push_back(o);
+      D->len[d].push_back(l);
+      o += l;
+    }
+  }
+  for (int c = 0; c < parts_k; ++c)
+    for (int a = 0; a < parts_i; ++a) {
+      jz_params sp = *p;
+      jz_solver* s = nullptr;
+      const int sn[3] = {dom_pad(D, 0, a), nj, dom_pad(D, 2, c)};
+      int rc = jz_create(sn[0], sn[1], sn[2], &sp, nullptr, 0, hip_stream, &s);
+      if (rc) {
+        jz_domain_destroy(D);
+        return rc;
+      }
+      // the split directions: advance [2, n - 2), ghost layers read, not wrapped
+      Interior in = s->in;
+      for (int d = 0; d < 3; ++d)
+        if ((D->halo >> d) & 1) {
+          in.bnd |= 1 << d;
+          in.lo[d] = 2;
+          in.hi[d] = sn[d] - 2;
+        }
+      s->in = in;
+      pick_tiling_for_device(sn[0], sn[1], sn[2], &sp, &s->tl, &in);
+      D->sub.push_back(s);
+    }
+  hipError_t e = hipMalloc((void**)&D->d_sub, D->sub.size() * sizeof(DomainSub));
+  if (e != hipSuccess) {
+    jz_domain_destroy(D);
+    return fail(JZ_ENOMEM, "jz_domain_create: %s", hipGetErrorString(e));
+  }
+  int rc = dom_upload_table(D);
+  if (rc) {
+    jz_domain_destroy(D);
+    return rc;
+  }
+  *out = D;
+  return JZ_OK;
+}
+
+int jz_domain_set_grid_metrics(jz_domain* D, const double* m) {
+  if (!D || !m) return fail(JZ_EINVAL, "jz_domain_set_grid_metrics: NULL argument");
+  std::vector<double> part;
+  for (int c = 0; c < D->parts[2]; ++c)
+    for (int a = 0; a < D->parts[0]; ++a) {
+      dom_extract(D, a, c, m, 10, part);
+      int rc = jz_set_grid_metrics(D->sub[dom_index(D, a, c)], part.data(), 0);
+      if (rc) return rc;
+    }
+  D->dt_valid = false;
+  return JZ_OK;
+}
+
+int jz_domain_set_state(jz_domain* D, const double* q) {
+  if (!D || !q) return fail(JZ_EINVAL, "jz_domain_set_state: NULL argument");
+  std::vector<double> part;
+  for (int c = 0; c < D->parts[2]; ++c)
+    for (int a = 0; a < D->parts[0]; ++a) {
+      dom_extract(D, a, c, q, 5, part);
+      int rc = jz_set_state(D->sub[dom_index(D, a, c)], part.data(), 0);
+      if (rc) return rc;
+    }
+  D->dt_valid = false;
+  return JZ_OK;
+}
+
+int jz_domain_advance(jz_domain* D, int nsteps) {
+  if (!D) return fail(JZ_EINVAL, "jz_domain_advance: NULL domain");
+  if (nsteps < 0) return fail(JZ_EINVAL, "jz_domain_advance: nsteps < 0");
+  for (jz_solver* s : D->sub)
+    if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_domain_advance: grid and state must be set first");
+  int rc = dom_ensure_dt(D);
+  if (rc) return rc;
+  const int ns = D->p.n_stages;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int k = 0; k < ns; ++k) {
+      for (jz_solver* s : D->sub) {
+        const void* in = k == 0 ? (const void*)s->q0 : dom_stage_out(s, k - 1, ns);
+        StageArgs a = stage_args(s, in, dom_stage_out(s, k, ns), s->p.rk_alpha[k]);
+        HIP_TRY(launch_stage(s, a, k, ns, false));
+      }
+      rc = dom_exchange(D, k, ns);
+      if (rc) return rc;
+    }
+    HIP_TRY(launch_domain_finalize(D->d_sub, (int)D->sub.size(), dom_ctl(D), D->stream));
+  }
+  return JZ_OK;
+}
+
+int jz_domain_get_state(jz_domain* D, double* q) {
+  if (!D || !q) return fail(JZ_EINVAL, "jz_domain_get_state: NULL argument");
+  std::vector<double> part;
+  int status = JZ_OK;
+  for (int c = 0; c < D->parts[2]; ++c)
+    for (int a = 0; a < D->parts[0]; ++a) {
+      jz_solver* s = D->sub[dom_index(D, a, c)];
+      part.assign(5 * (size_t)s->N, 0.0);
+      int rc = jz_get_state(s, part.data(), 0);
+      if (rc && rc != JZ_ENONFINITE) return rc;
+      if (rc) status = rc;
+      dom_insert(D, a, c, part, q);
+    }
+  return status;
+}
+
+int jz_domain_get_clock(jz_domain* D, double* t, double* next_dt, long long* steps) {
+  if (!D) return fail(JZ_EINVAL, "jz_domain_get_clock: NULL domain");
+  int rc = dom_ensure_dt(D);
+  if (rc) return rc;
+  return jz_get_clock(D->sub[0], t, next_dt, steps);
+}
+
+int jz_domain_get_residual_norms(jz_domain* D, double rms[5], double linf[5]) {
+  if (!D) return fail(JZ_EINVAL, "jz_domain_get_residual_norms: NULL domain");
+  return jz_get_residual_norms(D->sub[0], rms, linf);
+}
+
+int jz_domain_destroy(jz_domain* D) {
+  if (!D) return JZ_OK;
+  if (D->stream) (void)hipStreamSynchronize(D->stream);
+  for (jz_solver* s : D->sub) jz_destroy(s);
+  if (D->d_sub) (void)hipFree(D->d_sub);
+  delete D;
   return JZ_OK;
 }
 

@@ -525,4 +525,114 @@ hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, h
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// domains: one block split into sub-blocks with two ghost layers along each
+// split direction (the decomposition of Sec. 4.1, exchanged as in Sec. 4.3)
+// ---------------------------------------------------------------------------
+// Two node layers of direction d, all positions across it: dst layers dl0,
+// dl0 + 1 <- src layers sl0, sl0 + 1 (node-major, 5 values per node).  The
+// two blocks have the same extents across d.
+template <typename T>
+__global__ __launch_bounds__(256) void halo_copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int d, int n0d,
+                                                        int n1d, int n2d, int n0s, int n1s, int dl0, int sl0,
+                                                        long long count) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int v = (int)(t % 5);
+  const long long node = t / 5;
+  const int nd[3] = {n0d, n1d, n2d};
+  const int e = face_e(d), f = face_f(d);
+  const long long face = (long long)nd[e] * nd[f];
+  const int layer = (int)(node / face);
+  const long long r = node % face;
+  int c[3];
+  c[e] = (int)(r % nd[e]);
+  c[f] = (int)(r / nd[e]);
+  c[d] = dl0 + layer;
+  const long long id = c[0] + (long long)n0d * (c[1] + (long long)n1d * c[2]);
+  c[d] = sl0 + layer;
+  const long long is = c[0] + (long long)n0s * (c[1] + (long long)n1s * c[2]);
+  dst[5 * id + v] = src[5 * is + v];
+}
+
+hipError_t launch_halo_copy(void* dst, const void* src, bool is_float, int d, const int nd[3], const int nsrc[3],
+                            int dl0, int sl0, hipStream_t st) {
+  const int e = face_e(d), f = face_f(d);
+  const long long count = 2LL * nd[e] * nd[f] * 5;
+  const long long blocks = (count + 255) / 256;
+  if (is_float)
+    hipLaunchKernelGGL(halo_copy_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, (float*)dst,
+                       (const float*)src, d, nd[0], nd[1], nd[2], nsrc[0], nsrc[1], dl0, sl0, count);
+  else
+    hipLaunchKernelGGL(halo_copy_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, (double*)dst,
+                       (const double*)src, d, nd[0], nd[1], nd[2], nsrc[0], nsrc[1], dl0, sl0, count);
+  return hipGetLastError();
+}
+
+// dt of a domain's first step after a new state: the maximum of sum_d
+// lambda^d over every sub-block's advanced nodes (the lambda_max partials),
+// written to every sub-block's clock.
+__global__ __launch_bounds__(FIN_T) void domain_dt_kernel(const DomainSub* __restrict__ sub, int P, StepCtl ctl) {
+  __shared__ double red[FIN_T];
+  double lmax = 0.0;
+  for (int p = 0; p < P; ++p) lmax = max_nan(lmax, block_max(sub[p].lam_part, 1, sub[p].nb_lmax, red));
+  if (threadIdx.x == 0) {
+    const double dt = dt_rule(ctl, lmax);
+    const bool bad = !isfinite(lmax) || !isfinite(dt) || !(dt > 0.0);
+    for (int p = 0; p < P; ++p) {
+      sub[p].clock->lam_max = lmax;
+      sub[p].clock->dt = dt;
+      if (bad) *sub[p].flag |= 1;
+    }
+  }
+}
+
+// End of a domain step: the first-stage norms over all sub-blocks (sub-block
+// by sub-block, each in its fixed tile order), the clock advanced by the dt
+// just used, and the next dt from the last stage's lambda maxima of all
+// sub-blocks -- the same values in every sub-block's clock.
+__global__ __launch_bounds__(FIN_T) void domain_finalize_kernel(const DomainSub* __restrict__ sub, int P,
+                                                                StepCtl ctl) {
+  __shared__ double red[FIN_T];
+  for (int p = 0; p < P; ++p)
+    if (*sub[p].flag) return;  // a failed step froze the state
+  double sums[5] = {0, 0, 0, 0, 0}, maxs[5] = {0, 0, 0, 0, 0}, lmax = 0.0;
+  for (int p = 0; p < P; ++p) {
+    for (int v = 0; v < 5; ++v) {
+      sums[v] += block_sum(sub[p].norm_part + v, 10, sub[p].nb_tiles, red);
+      maxs[v] = max_nan(maxs[v], block_max(sub[p].norm_part + 5 + v, 10, sub[p].nb_tiles, red));
+    }
+    lmax = max_nan(lmax, block_max(sub[p].lam_part, 1, sub[p].nb_tiles, red));
+  }
+  if (threadIdx.x == 0) {
+    bool ok = isfinite(lmax);
+    for (int v = 0; v < 5; ++v) ok = ok && isfinite(sums[v]) && isfinite(maxs[v]);
+    const double dt = dt_rule(ctl, lmax);
+    ok = ok && isfinite(dt) && dt > 0.0;
+    for (int p = 0; p < P; ++p) {
+      Clock* c = sub[p].clock;
+      for (int v = 0; v < 5; ++v) {
+        c->rms[v] = sqrt(sums[v] * ctl.inv_n);
+        c->linf[v] = maxs[v];
+      }
+      c->t += c->dt;
+      c->steps += 1;
+      c->lam_max = lmax;
+      c->dt = dt;
+      if (!ok) *sub[p].flag |= 1;
+    }
+  }
+}
+
+hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st) {
+  hipLaunchKernelGGL(domain_dt_kernel, dim3(1), dim3(FIN_T), 0, st, sub, P, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st) {
+  hipLaunchKernelGGL(domain_finalize_kernel, dim3(1), dim3(FIN_T), 0, st, sub, P, ctl);
+  return hipGetLastError();
+}
+
 }  // namespace jz

@@ -106,6 +106,16 @@ struct BlockDesc {
   Phys ph;
 };
 
+// One sub-block of a domain, for the fixed-order reductions over all of them.
+struct DomainSub {
+  Clock* clock;
+  const double* norm_part;  // [nb_tiles][10] first-stage partials of its last step
+  const double* lam_part;   // lambda maxima: per tile, or per lambda_max block
+  int* flag;
+  int nb_tiles;             // stage-kernel workgroups (tiles) of the sub-block
+  int nb_lmax;              // lambda_max_kernel blocks of the sub-block
+};
+
 // The two directions of the faces normal to d, the faster first.
 __host__ __device__ inline int face_e(int d) { return d == 0 ? 1 : 0; }
 __host__ __device__ inline int face_f(int d) { return d == 2 ? 1 : 2; }
