@@ -107,3 +107,83 @@ def test_fullsize_bounded_jet_domain_one_step():
             inc_o = q1[v, centre] - qp[v, centre]
             inc_g = qg[v, n] - q[v, n]
             assert abs(inc_g - inc_o) <= 1e-9 * abs(inc_o) + 1e-15 * (1 + abs(q[v, n])), (c, v, inc_g, inc_o)
+
+
+def test_fullsize_cylinder_centreline_one_step():
+    """The cylindrical jet mesh of the benchmark (512 axial x 256 radial x 256
+    azimuths; jet exit, far field, centreline, periodic azimuth) with
+    Thomas-Lombard metrics computed from the coordinates, one step in the
+    benchmark's launch configuration:
+      * metrics equal the oracle's at every node (none on the axis), dt too;
+      * inflow layers held bitwise; every boundary layer -- the far-field
+        faces and the two centreline rings -- equals the oracle's boundary
+        rule applied to the GPU's own state;
+      * interior nodes at least 12 from every bounded face match the oracle
+        stepping a periodic patch around them;
+      * at sampled axial stations, the rings j = 0..11 of all 256 azimuths
+        match the oracle stepping the block of 21 stations x 24 rings x every
+        azimuth around them with the centreline rule (its artificial outer
+        face is 12 rings away, beyond the step's reach of 10)."""
+    import torch
+    from paper_2003_09926_amd import binding as B
+    assert torch.cuda.is_available()
+    print("[gpu-case] full size cylinder 512x256x256 one step", flush=True)
+    g, q, bc = I.jet_cylinder_case(DIMS, mach=1.4, seed=2)
+    mo = oracle.metrics_tl(*DIMS, g.x, g.y, g.z, g.period, bc=bc)
+    P = oracle.default_params(re_d=1.0e6, bc=bc)
+    dt, _ = oracle.cfl_dt(DIMS, P, mo, q)
+    with B.Solver(DIMS, B.params_default(re_d=1.0e6, bc=bc)) as s:
+        s.set_grid_coords(g.x, g.y, g.z, g.period)
+        mg = s.get_grid_metrics()
+        s.set_state(q)
+        dtg, _ = s.eval_dt()
+        s.advance(1)
+        qg = s.get_state()
+    ni, nj, nk = DIMS
+    fin = np.isfinite(mo[9])
+    assert np.array_equal(fin, np.isfinite(mg[9]))
+    assert not fin.reshape(nk, nj, ni)[:, 0, :].any()
+    scale = np.max(np.abs(mo[:9, fin]))
+    assert np.max(np.abs(mg[:9, fin] - mo[:9, fin])) <= 1e-13 * scale
+    assert np.max(np.abs(mg[9, fin] - mo[9, fin]) / mo[9, fin]) <= 1e-13
+    del mg
+    assert abs(dtg - dt) <= 1e-13 * dt
+    a = q.reshape(5, nk, nj, ni)
+    b = qg.reshape(5, nk, nj, ni)
+    np.testing.assert_array_equal(b[:, :, :, :2], a[:, :, :, :2])
+    qb = oracle.apply_bc(DIMS, P, mo, qg, q)
+    sc = np.abs(qg).max(axis=1, keepdims=True)
+    assert np.max(np.abs(qb - qg) / sc) <= 1e-13
+    del qb
+    rng = np.random.default_rng(14)
+    Pp = oracle.default_params(re_d=1.0e6)            # the interior patch is periodic
+    centre = R + (2 * R + 1) * (R + (2 * R + 1) * R)
+    for _ in range(8):
+        c = (int(rng.integers(12, ni - 12)), int(rng.integers(12, nj - 12)), int(rng.integers(0, nk)))
+        qp = patch(q, DIMS, c, R)
+        mp = patch(mo, DIMS, c, R)
+        q1, _, _, _ = oracle.step((2 * R + 1,) * 3, Pp, mp, qp, dt=dt)
+        n = flat(DIMS, *c)
+        for v in range(5):
+            inc_o = q1[v, centre] - qp[v, centre]
+            inc_g = qg[v, n] - q[v, n]
+            assert abs(inc_g - inc_o) <= 1e-9 * abs(inc_o) + 1e-15 * (1 + abs(q[v, n])), (c, v, inc_g, inc_o)
+    # centreline stations: 21 stations x 24 rings x all azimuths, periodic
+    # along the stations, the centreline below and a far-field face above
+    H = 24
+    Pa = oracle.default_params(re_d=1.0e6, bc=(0, 0, I.BC_AXIS, I.BC_FARFIELD, 0, 0))
+    M = mo.reshape(10, nk, nj, ni)
+    for i0 in (12, 200, ni - 13):
+        ii = np.arange(i0 - R, i0 + R + 1)
+        qa = np.ascontiguousarray(a[:, :, :H, :][:, :, :, ii]).reshape(5, -1)
+        ma = np.ascontiguousarray(M[:, :, :H, :][:, :, :, ii]).reshape(10, -1)
+        q1, _, _, _ = oracle.step((2 * R + 1, H, nk), Pa, ma, qa, dt=dt)
+        o = q1.reshape(5, nk, H, 2 * R + 1)[:, :, :12, R]
+        o0 = a[:, :, :12, i0]
+        gg = b[:, :, :12, i0]
+        inc_o, inc_g = o - o0, gg - o0
+        err = np.abs(inc_g - inc_o)
+        bound = 1e-9 * np.abs(inc_o) + 1e-15 * (1 + np.abs(o0))
+        assert np.all(err <= bound), (i0, float(np.max(err - bound)))
+        # the axis nodes of the station agree over the azimuth
+        assert np.all(gg[:, :, 0] == gg[:, :1, 0])
