@@ -1438,7 +1438,7 @@ int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int*
   if (best_ti < 0) {
     std::vector<std::pair<int, int>> cand;
     if (b->prec == JZ_FP64)
-      cand = {{32, 8}, {16, 16}, {28, 12}, {12, 12}};
+      cand = {{16, 12}, {32, 8}, {16, 16}, {28, 12}, {12, 12}};
     else
       cand = {{32, 16}, {28, 20}, {12, 12}};
     const int kcs[3] = {16, 32, 64};

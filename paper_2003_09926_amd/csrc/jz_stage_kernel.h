@@ -276,8 +276,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
   // LDS reads per flux column.  Where the registers do not allow it, the
   // stage keeps the ring: the FP32-flux first stage (norms at three waves
   // per SIMD) and, in the batch kernel, whose tile loop holds more
-  // registers, every stage with reductions.
-  constexpr bool ZREG = BASE == 0 || (!PERSIST && (BASE == 2 || (BASE == 1 && sizeof(Rl) == 8)));
+  // registers, every stage with reductions -- except in the compact FP64
+  // form, whose ring (93 KB of LDS) would leave one workgroup per CU: there
+  // the registers spill 40-48 bytes per lane instead, which costs less.
+  constexpr bool ZREG = BASE == 0 || ((!PERSIST || stage_compact<Rl, BX, BY>()) &&
+                                      (BASE == 2 || (BASE == 1 && sizeof(Rl) == 8)));
   constexpr int NPR = ZREG ? 1 : 3;
   // plane buffers (structure of arrays, one slot per tile column, rows of P)
   __shared__ Rl sPr[NPR][5][NS];   // u, v, w, T, p: the gradient plane, or a ring of three planes

@@ -43,8 +43,8 @@ def _members(B, cases, prec, tile, **extra):
     return ms
 
 
-@pytest.mark.parametrize("prec,tile", [(0, (28, 12)), (0, (12, 12)), (0, (32, 8)), (0, (16, 16)), (1, (28, 20)),
-                                       (1, (12, 12)), (1, (32, 16))])
+@pytest.mark.parametrize("prec,tile", [(0, (16, 12)), (0, (28, 12)), (0, (12, 12)), (0, (32, 8)), (0, (16, 16)),
+                                       (1, (28, 20)), (1, (12, 12)), (1, (32, 16))])
 def test_batch_members_bitwise_equal_alone(B, prec, tile):
     print(f"[gpu-case] batch vs alone precision={prec} tile={tile}", flush=True)
     cases = _cases()
@@ -118,7 +118,7 @@ def test_autotune_keeps_results(B, tmp_path):
     cache = str(tmp_path / "tune.txt")
     with B.Batch(ms) as b:
         choice, best_ms = b.autotune(trial_steps=1, cache_path=cache)
-        assert choice[0] in (28, 12) and best_ms > 0
+        assert tuple(choice[:2]) in {(16, 12), (32, 8), (16, 16), (28, 12), (12, 12)} and best_ms > 0
         b.advance(2)
         b.synchronize()
         choice2, _ = b.autotune(trial_steps=1, cache_path=cache)   # from the cache
