@@ -250,6 +250,19 @@ int jz_destroy(jz_solver* s);
 typedef struct jz_batch jz_batch;
 int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, jz_batch** out);
 int jz_batch_advance(jz_batch* b, int nsteps);
+/* Continuous batching: change the resident set between steps.  The step's
+ * launches read the member table and the work list from device memory, so
+ * the captured graph is replayed as it is (a new capture only when the
+ * tables must grow beyond their slots, which double each time).  add: the
+ * solver must match the batch (precision, stages, coefficients, tile shape;
+ * periodic, no statistics; grid and state set; JZ_EINVAL / JZ_ESTATE
+ * otherwise) and not be a member yet; it joins at the next jz_batch_advance
+ * with its own clock.  remove: waits for the batch's queued steps, then
+ * takes the member out; the caller keeps the solver.  A batch may be empty
+ * (its steps then do nothing).  members: the current member count. */
+int jz_batch_add(jz_batch* b, jz_solver* s);
+int jz_batch_remove(jz_batch* b, jz_solver* s);
+int jz_batch_members(jz_batch* b);
 /* Rebuild the member table after jz_set_tiling on members. */
 int jz_batch_refresh(jz_batch* b);
 /* 1 (default): replay a captured hipGraph per step; 0: launch directly. */

@@ -88,6 +88,9 @@ def library() -> ctypes.CDLL:
         "jz_get_tiling": ([S, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)], i),
         "jz_batch_create": ([ctypes.POINTER(S), i, ctypes.c_void_p, ctypes.POINTER(S)], i),
         "jz_batch_advance": ([S, i], i),
+        "jz_batch_add": ([S, S], i),
+        "jz_batch_remove": ([S, S], i),
+        "jz_batch_members": ([S], i),
         "jz_batch_refresh": ([S], i),
         "jz_batch_set_graph": ([S, i], i),
         "jz_batch_autotune": ([S, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i),
@@ -363,6 +366,22 @@ class Batch:
 
     def advance(self, nsteps: int):
         _check(library().jz_batch_advance(self._h, int(nsteps)), "jz_batch_advance")
+
+    def add(self, solver):
+        """Join a member between steps (no new capture of the step)."""
+        _check(library().jz_batch_add(self._h, solver._h), "jz_batch_add")
+        self.members.append(solver)
+
+    def remove(self, solver):
+        """Take a member out between steps; the caller keeps it."""
+        _check(library().jz_batch_remove(self._h, solver._h), "jz_batch_remove")
+        self.members = [m for m in self.members if m is not solver]
+
+    def __len__(self):
+        n = library().jz_batch_members(self._h)
+        if n < 0:
+            _check(n, "jz_batch_members")
+        return n
 
     def refresh(self):
         _check(library().jz_batch_refresh(self._h), "jz_batch_refresh")

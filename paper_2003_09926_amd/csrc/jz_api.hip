@@ -23,11 +23,11 @@ bool batch64_shape_supported(int bx, int by);
 int stage_wg_per_cu_fp64(int bx, int by);
 int stage_wg_per_cu_fp32(int bx, int by);
 bool batch32_shape_supported(int bx, int by);
-hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                                   int bx, int by, int grid_cap, int total, hipStream_t st);
-hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                                   int bx, int by, int grid_cap, int total, hipStream_t st);
-hipError_t launch_finalize_batch(const BlockDesc* desc, int nblk, hipStream_t st);
+hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                                   int bx, int by, hipStream_t st);
+hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                                   int bx, int by, hipStream_t st);
+hipError_t launch_finalize_batch(const BlockDesc* desc, BatchCtl* ctl, int slots, hipStream_t st);
 hipError_t launch_met32_to_soa(const float* m32, const double* jac, double* dst, long long N, hipStream_t st);
 hipError_t launch_stats_accumulate(const double* q, double* acc, long long N, double gamma, hipStream_t st);
 hipError_t launch_stats_finalize(const double* acc, long long N, double inv_n, double* out, hipStream_t st);
@@ -1137,15 +1137,18 @@ struct jz_batch {
   hipStream_t user;
   hipStream_t st;          // internal non-blocking stream (graph capture needs one)
   hipEvent_t ev_in, ev_out;
-  BlockDesc* d_desc;
-  int* d_off;
+  BlockDesc* d_desc;       // member table (cap slots)
+  int* d_off;              // first global tile of each member (cap + 1)
+  BatchCtl* d_ctl;         // work list read by the stage launches
+  int cap;                 // member slots of the device tables
   int total;               // tiles of all members
   long long npoints;
   bool use_graph, graph_ok;
   hipGraph_t graph;
   hipGraphExec_t exec;
   bool timing;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;       // recorded, not yet read
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;  // pool filled by jz_batch_set_timing
   double ms_acc;
   long long steps_acc;
 };
@@ -1160,7 +1163,11 @@ void batch_drop_graph(jz_batch* b) {
   b->graph_ok = false;
 }
 
-int batch_upload(jz_batch* b) {
+// Device tables of the current member set: descriptors, tile offsets and the
+// work list (members, tiles, the cost-weighted split among the XCD slots,
+// zeroed tile counters).  The captured step reads them from memory, so a
+// change of the member set needs no new capture.
+int batch_tables(jz_batch* b) {
   const int n = (int)b->m.size();
   std::vector<BlockDesc> d(n);
   std::vector<int> off(n + 1, 0);
@@ -1193,25 +1200,114 @@ int batch_upload(jz_batch* b) {
     b->npoints += s->N;
   }
   b->total = off[n];
-  HIP_TRY(hipMemcpyAsync(b->d_desc, d.data(), n * sizeof(BlockDesc), hipMemcpyHostToDevice, b->st));
+  // Split the tile list among the slots by plane steps: a tile of a chunk of
+  // L planes marches L + 2 of them, plus about two planes' worth of set-up and
+  // reductions.  Tiles are in each member's logical order (chunk by chunk).
+  BatchCtl c;
+  std::memset(&c, 0, sizeof c);
+  c.nblk = n;
+  c.total = b->total;
+  auto tile_cost = [](const jz_solver* s, int chunk) {
+    const int ek = s->in.hi[2] - s->in.lo[2];
+    const int len = std::min(s->tl.kchunk, ek - chunk * s->tl.kchunk);
+    return (long long)len + 4;
+  };
+  long long all = 0;
+  for (jz_solver* s : b->m)
+    for (int ch = 0; ch < s->tl.nchunks; ++ch) all += tile_cost(s, ch) * s->tl.tiles_i * s->tl.tiles_j;
+  int x = 1, g = 0;
+  long long acc = 0;
+  for (jz_solver* s : b->m)
+    for (int ch = 0; ch < s->tl.nchunks; ++ch) {
+      const long long w = tile_cost(s, ch);
+      for (int t = 0; t < s->tl.tiles_i * s->tl.tiles_j; ++t, ++g) {
+        while (x < kBatchSlots && acc * kBatchSlots >= all * x) c.split[x++] = g;
+        acc += w;
+      }
+    }
+  while (x <= kBatchSlots) c.split[x++] = g;
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(b->d_desc, d.data(), n * sizeof(BlockDesc), hipMemcpyHostToDevice, b->st));
+  }
   HIP_TRY(hipMemcpyAsync(b->d_off, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipMemcpyAsync(b->d_ctl, &c, sizeof c, hipMemcpyHostToDevice, b->st));
   HIP_TRY(hipStreamSynchronize(b->st));
+  return JZ_OK;
+}
+
+// new tables and a new capture (launch shapes changed)
+int batch_upload(jz_batch* b) {
+  int rc = batch_tables(b);
   batch_drop_graph(b);
+  return rc;
+}
+
+// Member slots of the device tables: grow to hold `need` members (a new
+// capture follows, since the finalize launch covers every slot).
+int batch_reserve(jz_batch* b, int need) {
+  if (need <= b->cap && b->d_desc) return JZ_OK;
+  int cap = b->cap > 0 ? b->cap : 16;
+  while (cap < need) cap *= 2;
+  if (b->st) HIP_TRY(hipStreamSynchronize(b->st));
+  BlockDesc* d = nullptr;
+  int* o = nullptr;
+  hipError_t e = hipMalloc((void**)&d, cap * sizeof(BlockDesc));
+  if (e == hipSuccess) e = hipMalloc((void**)&o, (cap + 1) * sizeof(int));
+  if (e != hipSuccess) {
+    if (d) (void)hipFree(d);
+    return fail(JZ_ENOMEM, "batch tables: %s", hipGetErrorString(e));
+  }
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_off) (void)hipFree(b->d_off);
+  b->d_desc = d;
+  b->d_off = o;
+  b->cap = cap;
+  batch_drop_graph(b);
+  return JZ_OK;
+}
+
+// What every member of a batch shares.
+struct BatchKind {
+  int prec, ns, bx, by;
+  double alpha[5];
+};
+
+BatchKind kind_of(const jz_solver* s) {
+  BatchKind k;
+  k.prec = s->prec;
+  k.ns = s->p.n_stages;
+  k.bx = s->tl.bx;
+  k.by = s->tl.by;
+  for (int i = 0; i < 5; ++i) k.alpha[i] = s->p.rk_alpha[i];
+  return k;
+}
+
+// A member must match the batch: precision, stages and coefficients, tile
+// shape; periodic, without statistics, with grid and state set.
+int batch_member_ok(const BatchKind& f, const jz_solver* s, const char* where, int i) {
+  if (!s) return fail(JZ_EINVAL, "%s: NULL member %d", where, i);
+  if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "%s: member %d has no grid or state", where, i);
+  if (s->p.n_stages < 2)
+    return fail(JZ_EINVAL, "%s: member %d has a single stage (batches need n_stages >= 2)", where, i);
+  if (s->prec != f.prec || s->p.n_stages != f.ns || s->tl.bx != f.bx || s->tl.by != f.by)
+    return fail(JZ_EINVAL, "%s: member %d differs in precision, stage count or tile shape", where, i);
+  for (int k = 0; k < f.ns; ++k)
+    if (s->p.rk_alpha[k] != f.alpha[k]) return fail(JZ_EINVAL, "%s: member %d has other stage coefficients", where, i);
+  if (s->in.bnd)
+    return fail(JZ_EINVAL, "%s: member %d has physical boundaries (batches take periodic blocks)", where, i);
+  if (s->stats) return fail(JZ_EINVAL, "%s: member %d collects statistics (not sampled in batches)", where, i);
   return JZ_OK;
 }
 
 // one full step of every member on b->st
 int batch_step_launches(jz_batch* b) {
-  const int n = (int)b->m.size();
   for (int k = 0; k < b->ns; ++k) {
     if (b->prec == JZ_FP64)
-      HIP_TRY(launch_stage_batch_fp64(b->d_desc, b->d_off, n, k, b->ns, b->alpha[k], b->bx, b->by, 0, b->total,
-                                      b->st));
+      HIP_TRY(launch_stage_batch_fp64(b->d_desc, b->d_off, b->d_ctl, k, b->ns, b->alpha[k], b->bx, b->by, b->st));
     else
-      HIP_TRY(launch_stage_batch_fp32(b->d_desc, b->d_off, n, k, b->ns, b->alpha[k], b->bx, b->by, 0, b->total,
-                                      b->st));
+      HIP_TRY(launch_stage_batch_fp32(b->d_desc, b->d_off, b->d_ctl, k, b->ns, b->alpha[k], b->bx, b->by, b->st));
   }
-  HIP_TRY(launch_finalize_batch(b->d_desc, n, b->st));
+  HIP_TRY(launch_finalize_batch(b->d_desc, b->d_ctl, b->cap, b->st));
   return JZ_OK;
 }
 
@@ -1237,21 +1333,12 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
   if (!members || nmembers < 1) return fail(JZ_EINVAL, "jz_batch_create: no members");
   jz_solver* f = members[0];
   if (!f) return fail(JZ_EINVAL, "jz_batch_create: NULL member");
+  const BatchKind kind = kind_of(f);
   for (int i = 0; i < nmembers; ++i) {
-    jz_solver* s = members[i];
-    if (!s) return fail(JZ_EINVAL, "jz_batch_create: NULL member %d", i);
-    if (!s->grid_set || !s->state_set) return fail(JZ_ESTATE, "jz_batch_create: member %d has no grid or state", i);
-    if (s->p.n_stages < 2)
-      return fail(JZ_EINVAL, "jz_batch_create: member %d has a single stage (batches need n_stages >= 2)", i);
-    if (s->prec != f->prec || s->p.n_stages != f->p.n_stages || s->tl.bx != f->tl.bx || s->tl.by != f->tl.by)
-      return fail(JZ_EINVAL, "jz_batch_create: member %d differs in precision, stage count or tile shape", i);
-    for (int k = 0; k < f->p.n_stages; ++k)
-      if (s->p.rk_alpha[k] != f->p.rk_alpha[k])
-        return fail(JZ_EINVAL, "jz_batch_create: member %d has other stage coefficients", i);
+    int rc = batch_member_ok(kind, members[i], "jz_batch_create", i);
+    if (rc) return rc;
     for (int j = 0; j < i; ++j)
-      if (members[j] == s) return fail(JZ_EINVAL, "jz_batch_create: member %d repeated", i);
-    if (s->in.bnd) return fail(JZ_EINVAL, "jz_batch_create: member %d has physical boundaries (batches take periodic blocks)", i);
-    if (s->stats) return fail(JZ_EINVAL, "jz_batch_create: member %d collects statistics (not sampled in batches)", i);
+      if (members[j] == members[i]) return fail(JZ_EINVAL, "jz_batch_create: member %d repeated", i);
   }
   const bool shape_ok = f->prec == JZ_FP64 ? batch64_shape_supported(f->tl.bx, f->tl.by)
                                             : batch32_shape_supported(f->tl.bx, f->tl.by);
@@ -1266,6 +1353,8 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
   b->user = (hipStream_t)hip_stream;
   b->d_desc = nullptr;
   b->d_off = nullptr;
+  b->d_ctl = nullptr;
+  b->cap = 0;
   b->use_graph = true;
   b->graph_ok = false;
   b->graph = nullptr;
@@ -1276,21 +1365,58 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
   hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_desc, nmembers * sizeof(BlockDesc));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_off, (nmembers + 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_ctl, sizeof(BatchCtl));
   for (jz_solver* s : b->m)
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
     jz_batch_destroy(b);
     return fail(JZ_EHIP, "jz_batch_create: %s", hipGetErrorString(e));
   }
-  int rc = batch_upload(b);
+  int rc = batch_reserve(b, nmembers);
+  if (rc == JZ_OK) rc = batch_upload(b);
   if (rc) {
     jz_batch_destroy(b);
     return rc;
   }
   *out = b;
   return JZ_OK;
+}
+
+int jz_batch_add(jz_batch* b, jz_solver* s) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_add: NULL batch");
+  if (!s) return fail(JZ_EINVAL, "jz_batch_add: NULL solver");
+  for (jz_solver* o : b->m)
+    if (o == s) return fail(JZ_EINVAL, "jz_batch_add: already a member");
+  BatchKind kind;
+  kind.prec = b->prec;
+  kind.ns = b->ns;
+  kind.bx = b->bx;
+  kind.by = b->by;
+  for (int k = 0; k < 5; ++k) kind.alpha[k] = b->alpha[k];
+  int rc = batch_member_ok(kind, s, "jz_batch_add", (int)b->m.size());
+  if (rc) return rc;
+  rc = batch_reserve(b, (int)b->m.size() + 1);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s->stream));  // the member's own set-up is done
+  HIP_TRY(hipStreamSynchronize(b->st));      // no step in flight reads the tables
+  b->m.push_back(s);
+  rc = batch_tables(b);
+  if (rc) b->m.pop_back();
+  return rc;
+}
+
+int jz_batch_remove(jz_batch* b, jz_solver* s) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_remove: NULL batch");
+  auto it = std::find(b->m.begin(), b->m.end(), s);
+  if (it == b->m.end()) return fail(JZ_EINVAL, "jz_batch_remove: not a member");
+  HIP_TRY(hipStreamSynchronize(b->st));  // the member's last step is done
+  b->m.erase(it);
+  return batch_tables(b);
+}
+
+int jz_batch_members(jz_batch* b) {
+  if (!b) return fail(JZ_EINVAL, "jz_batch_members: NULL batch");
+  return (int)b->m.size();
 }
 
 int jz_batch_set_graph(jz_batch* b, int enable) {
@@ -1338,8 +1464,14 @@ int jz_batch_advance(jz_batch* b, int nsteps) {
   for (int step = 0; step < nsteps; ++step) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (b->timing) {
-      HIP_TRY(hipEventCreate(&e0));
-      HIP_TRY(hipEventCreate(&e1));
+      if (b->ev_free.empty()) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+      } else {
+        e0 = b->ev_free.back().first;
+        e1 = b->ev_free.back().second;
+        b->ev_free.pop_back();
+      }
       HIP_TRY(hipEventRecord(e0, b->st));
     }
     if (b->use_graph) {
@@ -1364,14 +1496,22 @@ int jz_batch_advance(jz_batch* b, int nsteps) {
 int jz_batch_set_timing(jz_batch* b, int enable) {
   if (!b) return fail(JZ_EINVAL, "jz_batch_set_timing: NULL batch");
   HIP_TRY(hipStreamSynchronize(b->st));
-  for (auto& pr : b->ev) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
+  for (auto& pr : b->ev) b->ev_free.push_back(pr);
   b->ev.clear();
   b->ms_acc = 0;
   b->steps_acc = 0;
   b->timing = enable != 0;
+  // event pairs for the steps to come, so that none is created while steps are issued
+  while (b->timing && b->ev_free.size() < 256) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(JZ_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    b->ev_free.emplace_back(e0, e1);
+  }
   return JZ_OK;
 }
 
@@ -1383,8 +1523,7 @@ int jz_batch_get_timing(jz_batch* b, double* step_ms, long long* steps, long lon
     HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
     b->ms_acc += ms;
     b->steps_acc += 1;
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
+    b->ev_free.push_back(pr);
   }
   b->ev.clear();
   if (step_ms) *step_ms = b->ms_acc;
@@ -1528,8 +1667,13 @@ int jz_batch_destroy(jz_batch* b) {
     (void)hipEventDestroy(pr.second);
   }
   batch_drop_graph(b);
+  for (auto& pr : b->ev_free) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_off) (void)hipFree(b->d_off);
+  if (b->d_ctl) (void)hipFree(b->d_ctl);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->st) (void)hipStreamDestroy(b->st);

@@ -289,9 +289,14 @@ __global__ __launch_bounds__(FIN_T) void finalize_step_kernel(Clock* clk, const 
   finalize_step_body(clk, norm_part, lam_part, nb, ctl, flag, red);
 }
 
-// one workgroup per member block of a batch
-__global__ __launch_bounds__(FIN_T) void finalize_batch_kernel(const BlockDesc* __restrict__ desc) {
+// one workgroup per member slot of a batch (the table may hold fewer members
+// than the launch has workgroups); the first also zeroes the tile counters of
+// the stage launches for the next step
+__global__ __launch_bounds__(FIN_T) void finalize_batch_kernel(const BlockDesc* __restrict__ desc,
+                                                               BatchCtl* __restrict__ ctl) {
   __shared__ double red[FIN_T];
+  if (blockIdx.x == 0 && threadIdx.x < 5 * kBatchSlots) (&ctl->next[0][0])[threadIdx.x] = 0;
+  if ((int)blockIdx.x >= ctl->nblk) return;
   const BlockDesc& D = desc[blockIdx.x];
   finalize_step_body(D.clock, D.norm_part, D.lam_part, D.ntiles, D.ctl, D.flag, red);
 }
@@ -469,8 +474,8 @@ hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCt
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_batch(const BlockDesc* desc, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_batch_kernel, dim3(nblk), dim3(FIN_T), 0, st, desc);
+hipError_t launch_finalize_batch(const BlockDesc* desc, BatchCtl* ctl, int slots, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(slots), dim3(FIN_T), 0, st, desc, ctl);
   return hipGetLastError();
 }
 

@@ -106,6 +106,22 @@ struct BlockDesc {
   Phys ph;
 };
 
+// Work list of a batch, read by its persistent stage launches and kept in
+// device memory so that a captured step serves any resident set: the member
+// count, the tiles of all members (member by member, each in its logical
+// tile order), their split among the XCD slots (slot x takes global tiles
+// [split[x], split[x+1]), cut so that the slots get about equal numbers of
+// plane steps), and per stage and slot the number of tiles claimed so far
+// (the workgroups of a slot claim its tiles in order with an atomic add; the
+// finalize launch at the end of a step zeroes the counters for the next).
+constexpr int kBatchSlots = 8;
+struct BatchCtl {
+  int nblk;
+  int total;
+  int split[kBatchSlots + 1];
+  int next[5][kBatchSlots];
+};
+
 // One sub-block of a domain, for the fixed-order reductions over all of them.
 struct DomainSub {
   Clock* clock;

@@ -69,31 +69,31 @@ int stage_wg_per_cu_fp64(int bx, int by) {
 // persistent batch launches (FP64)
 // ---------------------------------------------------------------------------
 template <int BX, int BY, int MODE>
-static hipError_t batch_one64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                              int grid_cap, int total_tiles, hipStream_t st) {
+static hipError_t batch_one64(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                              hipStream_t st) {
   auto kern = stage_batch_kernel<double, double, double, false, BX, BY, MODE>;
   int per_cu = 0, dev = 0, ncu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, stage_threads<double, BX, BY>(), 0);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  // every resident workgroup (at least one per slot): the member set, and with
+  // it the tile count, may change between replays of a captured step
   int grid = per_cu * ncu;
-  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
-  if (grid > total_tiles) grid = total_tiles;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(stage_threads<double, BX, BY>()), 0, st, d, off, nblk, stage, ns, alpha);
+  if (grid < kBatchSlots) grid = kBatchSlots;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(stage_threads<double, BX, BY>()), 0, st, d, off, ctl, stage, ns, alpha);
   return hipGetLastError();
 }
 
 template <int BX, int BY>
-static hipError_t batch_shape64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                                int grid_cap, int total, hipStream_t st) {
+static hipError_t batch_shape64(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                                hipStream_t st) {
   const int mode = (stage == 0 ? 1 : 0) | (stage == ns - 1 ? 2 : 0);
   switch (mode) {
-    case 0: return batch_one64<BX, BY, 0>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-    case 1: return batch_one64<BX, BY, 1>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-    case 2: return batch_one64<BX, BY, 2>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-    default: return batch_one64<BX, BY, 3>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
+    case 0: return batch_one64<BX, BY, 0>(d, off, ctl, stage, ns, alpha, st);
+    case 1: return batch_one64<BX, BY, 1>(d, off, ctl, stage, ns, alpha, st);
+    case 2: return batch_one64<BX, BY, 2>(d, off, ctl, stage, ns, alpha, st);
+    default: return hipErrorInvalidValue;  // batches take at least two stages
   }
 }
 
@@ -102,13 +102,13 @@ bool batch64_shape_supported(int bx, int by) {
          (bx == 20 && by == 16);
 }
 
-hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                                   int bx, int by, int grid_cap, int total, hipStream_t st) {
-  if (bx == 32 && by == 16) return batch_shape64<32, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 16 && by == 16) return batch_shape64<16, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 36 && by == 12) return batch_shape64<36, 12>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 20 && by == 20) return batch_shape64<20, 20>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 20 && by == 16) return batch_shape64<20, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
+hipError_t launch_stage_batch_fp64(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                                   int bx, int by, hipStream_t st) {
+  if (bx == 32 && by == 16) return batch_shape64<32, 16>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 16 && by == 16) return batch_shape64<16, 16>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 36 && by == 12) return batch_shape64<36, 12>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 20 && by == 20) return batch_shape64<20, 20>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 20 && by == 16) return batch_shape64<20, 16>(d, off, ctl, stage, ns, alpha, st);
   return hipErrorInvalidValue;
 }
 

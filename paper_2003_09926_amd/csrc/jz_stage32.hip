@@ -68,40 +68,40 @@ int stage_wg_per_cu_fp32(int bx, int by) {
 // persistent batch launches (FP32-flux)
 // ---------------------------------------------------------------------------
 template <typename TIn, typename TOut, int BX, int BY, int MODE>
-static hipError_t batch_one32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                              int grid_cap, int total_tiles, hipStream_t st) {
+static hipError_t batch_one32(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                              hipStream_t st) {
   auto kern = stage_batch_kernel<float, TIn, TOut, true, BX, BY, MODE>;
   int per_cu = 0, dev = 0, ncu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, stage_threads<float, BX, BY>(), 0);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  // every resident workgroup (at least one per slot): the member set, and with
+  // it the tile count, may change between replays of a captured step
   int grid = per_cu * ncu;
-  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
-  if (grid > total_tiles) grid = total_tiles;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(stage_threads<float, BX, BY>()), 0, st, d, off, nblk, stage, ns, alpha);
+  if (grid < kBatchSlots) grid = kBatchSlots;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(stage_threads<float, BX, BY>()), 0, st, d, off, ctl, stage, ns, alpha);
   return hipGetLastError();
 }
 
 template <int BX, int BY>
-static hipError_t batch_shape32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                                int grid_cap, int total, hipStream_t st) {
-  if (stage == 0) return batch_one32<double, float, BX, BY, 1>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (stage == ns - 1) return batch_one32<float, double, BX, BY, 2>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  return batch_one32<float, float, BX, BY, 0>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
+static hipError_t batch_shape32(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                                hipStream_t st) {
+  if (stage == 0) return batch_one32<double, float, BX, BY, 1>(d, off, ctl, stage, ns, alpha, st);
+  if (stage == ns - 1) return batch_one32<float, double, BX, BY, 2>(d, off, ctl, stage, ns, alpha, st);
+  return batch_one32<float, float, BX, BY, 0>(d, off, ctl, stage, ns, alpha, st);
 }
 
 bool batch32_shape_supported(int bx, int by) {
   return (bx == 32 && by == 24) || (bx == 32 && by == 16) || (bx == 16 && by == 16) || (bx == 36 && by == 20);
 }
 
-hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, int nblk, int stage, int ns, double alpha,
-                                   int bx, int by, int grid_cap, int total, hipStream_t st) {
-  if (bx == 32 && by == 24) return batch_shape32<32, 24>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 32 && by == 16) return batch_shape32<32, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 16 && by == 16) return batch_shape32<16, 16>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
-  if (bx == 36 && by == 20) return batch_shape32<36, 20>(d, off, nblk, stage, ns, alpha, grid_cap, total, st);
+hipError_t launch_stage_batch_fp32(const BlockDesc* d, const int* off, BatchCtl* ctl, int stage, int ns, double alpha,
+                                   int bx, int by, hipStream_t st) {
+  if (bx == 32 && by == 24) return batch_shape32<32, 24>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 32 && by == 16) return batch_shape32<32, 16>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 16 && by == 16) return batch_shape32<16, 16>(d, off, ctl, stage, ns, alpha, st);
+  if (bx == 36 && by == 20) return batch_shape32<36, 20>(d, off, ctl, stage, ns, alpha, st);
   return hipErrorInvalidValue;
 }
 

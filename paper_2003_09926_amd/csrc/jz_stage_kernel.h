@@ -929,22 +929,27 @@ __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, BX, BY, MODE>()))) voi
 // global list (block b owns [tile_off[b], tile_off[b+1])).  Slot x (the XCD
 // that workgroups with blockIdx % 8 == x are dispatched to) takes a
 // contiguous share of the list, so neighbouring tiles of a block meet in one
-// L2; the workgroups of a slot walk its share with a fixed stride, and every
-// workgroup exits once its share is done.
+// L2; the workgroups of a slot claim its tiles one at a time, in order, from
+// the slot's counter, so a workgroup that drew short tiles takes more of
+// them, and every workgroup exits once its slot's share is claimed.  The
+// grid is at least kBatchSlots workgroups, so every slot is served.
 template <typename Rl, typename TIn, typename TOut, bool MET32, int BX, int BY, int MODE>
 __global__ __launch_bounds__((stage_threads<Rl, BX, BY>()))
 __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, BX, BY, MODE>()))) void stage_batch_kernel(const BlockDesc* __restrict__ desc,
-                                                             const int* __restrict__ tile_off, int nblk,
-                                                             int stage, int nstages, double alpha) {
-  // at most 8 slots, and never more slots than workgroups, so that every
-  // slot (and with it every tile) has at least one workgroup
-  const int NX = gridDim.x < 8 ? (int)gridDim.x : 8;
-  const int total = tile_off[nblk];
-  const int x = blockIdx.x % NX;
-  const int per_x = (gridDim.x - x + NX - 1) / NX;  // workgroups in this slot
-  const int w = blockIdx.x / NX;
-  const int lo = (int)((long long)total * x / NX), hi = (int)((long long)total * (x + 1) / NX);
-  for (int g = lo + w; g < hi; g += per_x) {
+                                                             const int* __restrict__ tile_off,
+                                                             BatchCtl* __restrict__ ctl, int stage, int nstages,
+                                                             double alpha) {
+  __shared__ int sTile;
+  const int x = blockIdx.x % kBatchSlots;
+  const int nblk = ctl->nblk;
+  const int lo = ctl->split[x], hi = ctl->split[x + 1];
+  int* next = &ctl->next[stage][x];
+  for (;;) {
+    __syncthreads();  // the previous tile's LDS readers are done, and sTile is free
+    if (threadIdx.x == 0) sTile = lo + atomicAdd(next, 1);
+    __syncthreads();
+    const int g = sTile;
+    if (g >= hi) break;
     // block owning global tile g (uniform over the workgroup)
     int a = 0, b = nblk;
     while (b - a > 1) {
@@ -975,7 +980,6 @@ __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<Rl, BX, BY, MODE>()))) voi
     A.nchunks = D.nchunks;
     A.in = D.in;
     A.ph = D.ph;
-    __syncthreads();  // the previous tile's LDS readers are done
     stage_tile<Rl, TIn, TOut, MET32, BX, BY, MODE, true>(A, g - tile_off[a]);
   }
 }

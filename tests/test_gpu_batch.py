@@ -191,3 +191,95 @@ def test_tiny_batch_with_fewer_tiles_than_xcds(B):
         assert np.array_equal(a.get_state(), c.get_state())
         a.close()
         c.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_add_remove_bitwise_equal_alone(B, prec):
+    """Continuous batching: members join and leave between steps (the step
+    graph is not captured again) and each still comes out bitwise equal to
+    the block advanced alone for the same number of steps; the batch may run
+    empty; growing past the table slots (16) keeps the results too."""
+    print(f"[gpu-case] batch add/remove precision={prec}", flush=True)
+    cases = _cases()
+    tile = (0, 0)
+    alone = []
+    # steps each member takes in the batch below
+    for (g, q, kw), n in zip(cases, [4, 3, 3, 3, 1, 1]):
+        with B.Solver(g.dims, B.params_default(precision=prec, **kw)) as s:
+            s.set_grid_metrics(g.metrics)
+            s.set_state(q)
+            s.advance(n)
+            alone.append((s.get_state(), s.clock()))
+    ms = _members(B, cases, prec, tile)
+    b = B.Batch(ms[:2])
+    b.advance(1)                 # members 0, 1
+    b.add(ms[2])
+    b.add(ms[3])
+    b.advance(1)                 # 0, 1, 2, 3
+    b.remove(ms[1])
+    b.add(ms[4])
+    b.advance(1)                 # 0, 2, 3, 4
+    b.remove(ms[3])
+    b.remove(ms[4])
+    b.add(ms[5])
+    b.add(ms[1])
+    b.advance(1)                 # 0, 2, 5, 1
+    b.remove(ms[0])
+    b.remove(ms[2])
+    b.remove(ms[5])
+    b.remove(ms[1])
+    assert len(b) == 0
+    b.advance(1)                 # empty
+    b.add(ms[3])
+    b.advance(1)                 # 3
+    b.synchronize()
+    b.close()
+    for s, (q, clk) in zip(ms, alone):
+        assert np.array_equal(s.get_state(), q)
+        assert s.clock() == clk
+        s.close()
+
+
+def test_batch_grows_past_its_table_slots(B):
+    print("[gpu-case] batch growth past 16 members", flush=True)
+    small = [(I.uniform_box(9 + (i % 5), 11 + (i % 3), 13 + (i % 4)), 1.2 + 0.03 * i, 200 + i) for i in range(21)]
+    solo, members = [], []
+    for g, mach, seed in small:
+        q = I.jet_state(g, mach, seed)
+        for store in (solo, members):
+            s = B.Solver(g.dims, B.params_default(mach_j=mach))
+            s.set_grid_metrics(g.metrics)
+            s.set_state(q)
+            store.append(s)
+    b = B.Batch(members[:1])
+    b.advance(1)
+    for s in members[1:]:
+        b.add(s)
+    b.advance(2)
+    b.synchronize()
+    b.close()
+    solo[0].advance(3)
+    for s in solo[1:]:
+        s.advance(2)
+    for a, c in zip(solo, members):
+        assert np.array_equal(a.get_state(), c.get_state())
+        a.close()
+        c.close()
+
+
+def test_batch_add_remove_rejections(B):
+    cases = _cases()[:3]
+    a, c = _members(B, cases[:2], 0, (0, 0))
+    f32 = _members(B, cases[2:], 1, (0, 0))[0]
+    other_tile = _members(B, cases[2:], 0, (16, 16))[0]
+    with B.Batch([a]) as b:
+        for bad in (a, f32, other_tile):
+            with pytest.raises(B.JzError) as ei:
+                b.add(bad)
+            assert ei.value.code == B.JZ_EINVAL
+        with pytest.raises(B.JzError):
+            b.remove(c)           # not a member
+        b.add(c)
+        assert len(b) == 2
+    for s in (a, c, f32, other_tile):
+        s.close()
