@@ -309,7 +309,7 @@ def run_batch(prec_name: str, steps: int, warmup: int):
     }
 
 
-def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "streams"):
+def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "batch"):
     """Config 5: Poisson arrivals (mean 20 runs/s, seed 5) of cubic jet runs
     n^3, n uniform in [48, 192], Mach U[1.2, 2.0], Re_D log-uniform
     [1e5, 1e6], 200 steps each at CFL 0.5, admitted under a 200 GB budget,
@@ -325,6 +325,7 @@ def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "st
     tile = None  # the library's default tiling for the precision
     stream = I.arrival_stream(seed=5, nruns=nruns, rate=20.0)
     runs = S.make_runs(stream)
+    S.attach_payloads(runs)   # the clients' requests: payloads in host memory before the clock starts
     srv = S.JetServer(precision=prec, budget_bytes=200 << 30, max_resident=32, chunk_steps=20, tile=tile,
                       mode=mode)
     st = srv.serve(runs)
@@ -337,7 +338,9 @@ def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "st
         "data": "synthetic",
         "config": {"workload": f"served_jet_runs_{prec_name}", "runs": nruns, "arrival_rate_per_s": 20.0,
                    "n_range": [48, 192], "steps_per_run": 200, "budget_gb": 200, "max_resident": 32,
-                   "chunk_steps": 20, "seed": 5, "form": f"serve-{prec_name}", "mode": mode},
+                   "chunk_steps": 20, "seed": 5, "form": f"serve-{prec_name}", "mode": mode,
+                   "admit_until_tiles_per_cu": srv.tiles_per_cu, "member_kchunk": srv.kchunk,
+                   "payload": "host arrays built before the clock starts, uploaded at admission"},
         "serve": summ,
     }
     if with_sequential:
@@ -360,8 +363,8 @@ def main(argv=None):
     ap.add_argument("--no-error", action="store_true", help="fp32 form: skip the error-vs-oracle run")
     ap.add_argument("--runs", type=int, default=100, help="serve forms: length of the arrival stream")
     ap.add_argument("--no-sequential", action="store_true", help="serve forms: skip the alone baseline")
-    ap.add_argument("--serve-mode", default="streams", choices=["streams", "batch"],
-                    help="serve forms: resident runs on their own streams, or one batch over them")
+    ap.add_argument("--serve-mode", default="batch", choices=["streams", "batch"],
+                    help="serve forms: one batch over the resident runs, or each run on its own stream")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true",
                     help="fp64 form: skip the FP32-flux form timed on the same workload")

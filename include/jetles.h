@@ -257,9 +257,13 @@ int jz_batch_advance(jz_batch* b, int nsteps);
  * solver must match the batch (precision, stages, coefficients, tile shape;
  * periodic, no statistics; grid and state set; JZ_EINVAL / JZ_ESTATE
  * otherwise) and not be a member yet; it joins at the next jz_batch_advance
- * with its own clock.  remove: waits for the batch's queued steps, then
- * takes the member out; the caller keeps the solver.  A batch may be empty
- * (its steps then do nothing).  members: the current member count. */
+ * with its own clock (its set-up on its own stream is ordered before the
+ * batch's next step).  remove: takes the member out; work issued afterwards
+ * on the member's own stream follows the batch steps queued so far (the
+ * last ones that include it); the caller keeps the solver.  Neither call
+ * waits for the device: the table change is queued behind the steps in
+ * flight.  A batch may be empty (its steps then do nothing).  members: the
+ * current member count. */
 int jz_batch_add(jz_batch* b, jz_solver* s);
 int jz_batch_remove(jz_batch* b, jz_solver* s);
 int jz_batch_members(jz_batch* b);

@@ -194,8 +194,17 @@ void pick_tiling_for_device(int ni, int nj, int nk, const jz_params* p, Tiling* 
   // The compact FP64 shape (16 x 12 tiles, two workgroups per CU) runs its
   // workgroups unsynchronised, so the rounds model does not hold for it;
   // chunks of 64 planes measured best on 512 x 256 x 256 (32: +2 %, 128: +6 %).
+  // A block too small to give every resident workgroup slot a tile with
+  // such chunks takes shorter ones, as many as fill the device.
   const bool compact = (!p || p->precision == JZ_FP64) && t->bx == 20 && t->by == 16;
-  const int kc = compact ? (ek < 64 ? ek : 64) : auto_kchunk(t->tiles_i * t->tiles_j, ek, (long long)per_cu * ncu);
+  const long long slots = (long long)per_cu * ncu, tiles = (long long)t->tiles_i * t->tiles_j;
+  int kc = 0;
+  if (compact) {
+    kc = ek < 64 ? ek : 64;
+    if (tiles * ((ek + kc - 1) / kc) < slots) kc = auto_kchunk((int)tiles, ek, slots);
+  } else {
+    kc = auto_kchunk((int)tiles, ek, slots);
+  }
   t->kchunk = kc;
   t->nchunks = (ek + kc - 1) / kc;
   t->nblocks = t->tiles_i * t->tiles_j * t->nchunks;
@@ -1151,6 +1160,15 @@ struct jz_batch {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;  // pool filled by jz_batch_set_timing
   double ms_acc;
   long long steps_acc;
+  // Pinned staging buffers of the table uploads, each with the event of its
+  // last copy: a change of the member set is queued on the batch's stream
+  // behind the steps in flight instead of waiting for them.
+  static constexpr int kStage = 4;
+  char* h_stage[kStage];
+  hipEvent_t ev_stage[kStage];
+  size_t stage_bytes;
+  int stage_next;
+  hipEvent_t ev_member;    // orders a joining or leaving member's stream against the batch's
 };
 
 namespace {
@@ -1167,10 +1185,20 @@ void batch_drop_graph(jz_batch* b) {
 // work list (members, tiles, the cost-weighted split among the XCD slots,
 // zeroed tile counters).  The captured step reads them from memory, so a
 // change of the member set needs no new capture.
+// byte offsets of the parts of a staging buffer: work list, tile offsets, descriptors
+size_t stage_off_ofs() { return align_up(sizeof(BatchCtl)); }
+size_t stage_desc_ofs(int cap) { return align_up(stage_off_ofs() + (cap + 1) * sizeof(int)); }
+size_t stage_size(int cap) { return stage_desc_ofs(cap) + cap * sizeof(BlockDesc); }
+
 int batch_tables(jz_batch* b) {
   const int n = (int)b->m.size();
-  std::vector<BlockDesc> d(n);
-  std::vector<int> off(n + 1, 0);
+  const int si = b->stage_next;
+  b->stage_next = (si + 1) % jz_batch::kStage;
+  HIP_TRY(hipEventSynchronize(b->ev_stage[si]));  // the buffer's previous copy is done
+  char* h = b->h_stage[si];
+  BlockDesc* d = reinterpret_cast<BlockDesc*>(h + stage_desc_ofs(b->cap));
+  int* off = reinterpret_cast<int*>(h + stage_off_ofs());
+  off[0] = 0;
   b->npoints = 0;
   for (int i = 0; i < n; ++i) {
     jz_solver* s = b->m[i];
@@ -1203,7 +1231,7 @@ int batch_tables(jz_batch* b) {
   // Split the tile list among the slots by plane steps: a tile of a chunk of
   // L planes marches L + 2 of them, plus about two planes' worth of set-up and
   // reductions.  Tiles are in each member's logical order (chunk by chunk).
-  BatchCtl c;
+  BatchCtl& c = *reinterpret_cast<BatchCtl*>(h);
   std::memset(&c, 0, sizeof c);
   c.nblk = n;
   c.total = b->total;
@@ -1226,12 +1254,10 @@ int batch_tables(jz_batch* b) {
       }
     }
   while (x <= kBatchSlots) c.split[x++] = g;
-  if (n > 0) {
-    HIP_TRY(hipMemcpyAsync(b->d_desc, d.data(), n * sizeof(BlockDesc), hipMemcpyHostToDevice, b->st));
-  }
-  HIP_TRY(hipMemcpyAsync(b->d_off, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->st));
+  if (n > 0) HIP_TRY(hipMemcpyAsync(b->d_desc, d, n * sizeof(BlockDesc), hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipMemcpyAsync(b->d_off, off, (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->st));
   HIP_TRY(hipMemcpyAsync(b->d_ctl, &c, sizeof c, hipMemcpyHostToDevice, b->st));
-  HIP_TRY(hipStreamSynchronize(b->st));
+  HIP_TRY(hipEventRecord(b->ev_stage[si], b->st));
   return JZ_OK;
 }
 
@@ -1263,6 +1289,14 @@ int batch_reserve(jz_batch* b, int need) {
   b->d_off = o;
   b->cap = cap;
   batch_drop_graph(b);
+  // staging buffers for the new size (the stream sync above finished their copies)
+  for (int i = 0; i < jz_batch::kStage; ++i) {
+    if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
+    b->h_stage[i] = nullptr;
+    e = hipHostMalloc((void**)&b->h_stage[i], stage_size(cap), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(JZ_ENOMEM, "batch staging: %s", hipGetErrorString(e));
+  }
+  b->stage_bytes = stage_size(cap);
   return JZ_OK;
 }
 
@@ -1355,6 +1389,13 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
   b->d_off = nullptr;
   b->d_ctl = nullptr;
   b->cap = 0;
+  for (int i = 0; i < jz_batch::kStage; ++i) {
+    b->h_stage[i] = nullptr;
+    b->ev_stage[i] = nullptr;
+  }
+  b->stage_bytes = 0;
+  b->stage_next = 0;
+  b->ev_member = nullptr;
   b->use_graph = true;
   b->graph_ok = false;
   b->graph = nullptr;
@@ -1366,6 +1407,9 @@ int jz_batch_create(jz_solver* const* members, int nmembers, void* hip_stream, j
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_ctl, sizeof(BatchCtl));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_member, hipEventDisableTiming);
+  for (int i = 0; i < jz_batch::kStage; ++i)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_stage[i], hipEventDisableTiming);
   for (jz_solver* s : b->m)
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
@@ -1397,8 +1441,9 @@ int jz_batch_add(jz_batch* b, jz_solver* s) {
   if (rc) return rc;
   rc = batch_reserve(b, (int)b->m.size() + 1);
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(s->stream));  // the member's own set-up is done
-  HIP_TRY(hipStreamSynchronize(b->st));      // no step in flight reads the tables
+  // the batch's next steps follow the member's own set-up
+  HIP_TRY(hipEventRecord(b->ev_member, s->stream));
+  HIP_TRY(hipStreamWaitEvent(b->st, b->ev_member, 0));
   b->m.push_back(s);
   rc = batch_tables(b);
   if (rc) b->m.pop_back();
@@ -1409,7 +1454,10 @@ int jz_batch_remove(jz_batch* b, jz_solver* s) {
   if (!b) return fail(JZ_EINVAL, "jz_batch_remove: NULL batch");
   auto it = std::find(b->m.begin(), b->m.end(), s);
   if (it == b->m.end()) return fail(JZ_EINVAL, "jz_batch_remove: not a member");
-  HIP_TRY(hipStreamSynchronize(b->st));  // the member's last step is done
+  // whatever the caller issues next on the member's stream follows the steps
+  // queued so far, the last ones that include it
+  HIP_TRY(hipEventRecord(b->ev_member, b->st));
+  HIP_TRY(hipStreamWaitEvent(s->stream, b->ev_member, 0));
   b->m.erase(it);
   return batch_tables(b);
 }
@@ -1674,6 +1722,11 @@ int jz_batch_destroy(jz_batch* b) {
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_off) (void)hipFree(b->d_off);
   if (b->d_ctl) (void)hipFree(b->d_ctl);
+  for (int i = 0; i < jz_batch::kStage; ++i) {
+    if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
+    if (b->ev_stage[i]) (void)hipEventDestroy(b->ev_stage[i]);
+  }
+  if (b->ev_member) (void)hipEventDestroy(b->ev_member);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->st) (void)hipStreamDestroy(b->st);

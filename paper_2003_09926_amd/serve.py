@@ -1,28 +1,32 @@
 """Served form: a request loop with continuous batching.
 
-Jet runs arrive over (wall-clock) time and are served first come, first
-served.  A run is admitted when it has arrived, a slot is free, its device
-footprint fits the HBM budget, and the runs already resident do not yet give
-the stage kernel enough workgroups to fill the device (``fill_tiles``, one
-round of workgroups); its grid and initial state are then built directly in
-device memory and it joins the resident set.  Small runs thus share the GPU
-until together they fill it, while a run that fills it by itself runs alone
-and keeps first-come latency.  The resident set advances in chunks of steps no
-longer than the shortest remaining run, so runs that arrive while others are
-on the GPU join at the next chunk and finished runs leave, freeing their slot
-and memory.  Each run keeps its own state, metrics, clock and time step in
-HBM for its whole life.  Two ways of advancing the resident set:
+Jet runs arrive over (wall-clock) time, each with its payload (the grid's
+metric set and the initial state, built by the client in host memory), and
+are served first come, first served.  A run is admitted when it has arrived,
+a slot is free, its device footprint fits the HBM budget, and the runs
+already resident do not yet give the stage kernels ``tiles_per_cu`` tiles per
+compute unit (8: enough that the tail of each stage launch, where the last
+tiles finish while other workgroups find no more, stays short; fewer tiles
+cost throughput, more cost latency); its payload is then uploaded
+and the run joins the resident set, where its state, metrics, clock and time
+step stay in HBM for its whole life.  The resident set advances in chunks of
+steps no longer than the shortest remaining run, so runs that arrive while
+others are on the GPU join at the next chunk and finished runs leave,
+freeing their slot and memory.  Two ways of advancing the resident set:
 
-* ``mode="streams"`` (default): every run owns a HIP stream and the chunk of
-  each resident run is issued on it, so the device runs the stage kernels of
-  small runs side by side; joining and leaving cost nothing;
-* ``mode="batch"``: one batch over all resident runs (one persistent launch
-  per RK stage, step replayed from a hipGraph), rebuilt when the resident set
-  changes.
+* ``mode="batch"`` (default): one batch over all resident runs -- one
+  persistent launch per RK stage whose workgroups claim the tiles of every
+  member, the step replayed from a hipGraph captured once; runs join and
+  leave with ``Batch.add`` / ``Batch.remove`` (no new capture).  Members
+  march chunks of ``batch_kchunk`` planes: the batch fills the device with
+  many members, so no run needs short chunks to fill it by itself;
+* ``mode="streams"``: every run owns a HIP stream and its steps are issued
+  on it, so the device runs the stage kernels of small runs side by side.
 
-The host never waits for a chunk, only for a run that completes.
-All GPU arithmetic happens in the HIP library through the C ABI; this module
-only schedules.
+The host never waits for a chunk, only for a run that completes (and, in
+batch mode, for the queued steps when the member set changes).  All GPU
+arithmetic happens in the HIP library through the C ABI; this module only
+schedules.
 """
 from __future__ import annotations
 
@@ -55,6 +59,7 @@ class Run:
     stream: object = None
     result: Optional[np.ndarray] = None
     ok: bool = True
+    payload: Optional[tuple] = None   # (metrics 10 x N, state 5 x N), host arrays
 
     @property
     def points(self) -> int:
@@ -70,28 +75,40 @@ def make_runs(stream: List[dict]) -> List[Run]:
             for r, s in enumerate(stream)]
 
 
-def _params(run: Run, precision: int, tile):
-    """Solver parameters of a run; tile None leaves the tiling to the library."""
+def _params(run: Run, precision: int, tile, kchunk: int = 0):
+    """Solver parameters of a run; tile None (kchunk 0) leaves the tiling
+    (the chunk length) to the library."""
     return B.params_default(precision=precision, mach_j=run.mach, re_d=run.re_d,
-                            tile_i=tile[0] if tile else 0, tile_j=tile[1] if tile else 0)
+                            tile_i=tile[0] if tile else 0, tile_j=tile[1] if tile else 0, kchunk=kchunk)
 
 
-def start_run(run: Run, precision: int, tile, device="cuda", stream=None) -> B.Solver:
-    """Allocate the run's workspace, build its uniform jet box in device
-    memory (on ``stream``, the run's own stream, when given) and hand grid and
-    state to the library."""
+def make_payload(run: Run) -> tuple:
+    """The request's payload as a client builds it: the uniform jet box's
+    metric set and initial state in host memory."""
+    g, q = I.jet_box_case(run.dims, mach=run.mach, seed=run.seed)
+    return g.metrics, q
+
+
+def attach_payloads(runs: List[Run]) -> None:
+    for r in runs:
+        if r.payload is None:
+            r.payload = make_payload(r)
+
+
+def start_run(run: Run, precision: int, tile, kchunk: int = 0, stream=None) -> B.Solver:
+    """Allocate the run's workspace and upload its payload (on ``stream``,
+    the run's own stream, when given)."""
     import torch
     st = stream if stream is not None else torch.cuda.current_stream()
-    with torch.cuda.stream(st):
-        s = B.Solver(run.dims, _params(run, precision, tile), stream=st)
-        m, q = I.jet_box_device(run.dims, run.mach, run.seed, device)
-        s.set_grid_metrics(m)
-        s.set_state(q.reshape(-1))
+    m, q = run.payload if run.payload is not None else make_payload(run)
+    s = B.Solver(run.dims, _params(run, precision, tile, kchunk), stream=st)
+    s.set_grid_metrics(m)
+    s.set_state(q)
     return s
 
 
-def footprint(run: Run, precision: int, tile) -> int:
-    return B.workspace_bytes(run.dims, _params(run, precision, tile))
+def footprint(run: Run, precision: int, tile, kchunk: int = 0) -> int:
+    return B.workspace_bytes(run.dims, _params(run, precision, tile, kchunk))
 
 
 def stage_tiles(solver: B.Solver) -> int:
@@ -131,7 +148,7 @@ class JetServer:
 
     def __init__(self, precision: int = B.JZ_FP64, budget_bytes: int = 200 << 30, max_resident: int = 64,
                  chunk_steps: int = 20, tile=None, keep_results: bool = False, fill_tiles: Optional[int] = None,
-                 mode: str = "streams"):
+                 mode: str = "batch", tiles_per_cu: float = 8.0, batch_kchunk: int = 32):
         if mode not in ("streams", "batch"):
             raise ValueError("mode is 'streams' or 'batch'")
         self.mode = mode
@@ -141,9 +158,11 @@ class JetServer:
         self.chunk = int(chunk_steps)
         self.tile = tuple(tile) if tile else None
         self.keep_results = keep_results
-        # workgroups that fill the device for one round of the stage kernel
-        # (None: taken from the first admitted run's occupancy)
+        # resident tiles at which admission stops (None: tiles_per_cu times
+        # the compute units, read from the first admitted run)
         self.fill_tiles = fill_tiles
+        self.tiles_per_cu = float(tiles_per_cu)
+        self.kchunk = int(batch_kchunk) if mode == "batch" else 0
 
     def serve(self, runs: List[Run], time_scale: float = 1.0) -> ServeStats:
         """Play the arrival stream (arrival times scaled by time_scale) and
@@ -151,20 +170,43 @@ class JetServer:
         import torch
         pending = deque(sorted(runs, key=lambda r: r.arrival))
         resident: List[Run] = []
+        finishing: List[Run] = []     # done on the device (or queued to be), results not read yet
         batch: Optional[B.Batch] = None
         used, used_tiles = 0, 0
         max_res, max_bytes, chunks, failed = 0, 0, 0, 0
         point_stages = 0.0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        while pending or resident:
-            changed = False
-            # admission: arrived, a free slot, and the footprint fits the budget
+        upload_s, collect_s = 0.0, 0.0   # host time in admissions (uploads) and in reading results
+
+        def collect(rs):
+            nonlocal used, failed, collect_s
+            tc = time.perf_counter()
+            for r in rs:
+                try:
+                    # on the run's own stream, which follows its last step
+                    out = r.solver.get_state() if self.keep_results else None
+                    r.solver.residual_norms()
+                except B.JzError:
+                    r.ok = False
+                    failed += 1
+                    out = None
+                r.result = out
+                r.finished = now()
+                r.solver.close()
+                r.solver = None
+                used -= r.footprint
+            collect_s += time.perf_counter() - tc
+
+        while pending or resident or finishing:
+            # admission: arrived, a free slot, the footprint fits the budget,
+            # and the resident runs do not fill the device yet; the payload
+            # upload overlaps the steps already queued
             while pending and pending[0].arrival * time_scale <= now() and len(resident) < self.max_resident:
                 if resident and self.fill_tiles is not None and used_tiles >= self.fill_tiles:
-                    break                      # the resident runs already fill the device
+                    break
                 r = pending[0]
-                fp = footprint(r, self.precision, self.tile)
+                fp = footprint(r, self.precision, self.tile, self.kchunk)
                 if fp > self.budget:
                     pending.popleft()          # can never fit: reject
                     r.ok, r.finished = False, now()
@@ -173,88 +215,77 @@ class JetServer:
                 if used + fp > self.budget:
                     break
                 pending.popleft()
+                tu = time.perf_counter()
                 r.footprint = fp
                 r.stream = torch.cuda.Stream() if self.mode == "streams" else None
-                r.solver = start_run(r, self.precision, self.tile, stream=r.stream)
+                r.solver = start_run(r, self.precision, self.tile, self.kchunk, stream=r.stream)
                 r.tiles = stage_tiles(r.solver)
                 if self.fill_tiles is None:
-                    per_cu, cus = r.solver.occupancy()
-                    self.fill_tiles = max(1, per_cu) * cus
+                    _, cus = r.solver.occupancy()
+                    self.fill_tiles = int(self.tiles_per_cu * cus)
+                if self.mode == "batch":
+                    if batch is None:
+                        batch = B.Batch([r.solver])
+                        batch.set_timing(True)
+                    else:
+                        batch.add(r.solver)
+                upload_s += time.perf_counter() - tu
                 r.admitted = now()
                 r.remaining = r.steps
                 used += fp
                 used_tiles += r.tiles
                 resident.append(r)
-                changed = True
             max_res = max(max_res, len(resident))
             max_bytes = max(max_bytes, used)
+            earlier, finishing = finishing, []
+            if resident:
+                # Enqueue the next chunk without waiting for the device: the
+                # host knows every run's progress, and the streams order the work.
+                n = min(self.chunk, min(r.remaining for r in resident))
+                if self.mode == "batch":
+                    batch.advance(n)
+                else:
+                    for r in resident:
+                        r.solver.advance(n)
+                chunks += 1
+                point_stages += sum(r.points for r in resident) * 5.0 * n
+                for r in list(resident):
+                    r.remaining -= n
+                    if r.remaining == 0:
+                        if batch is not None:
+                            batch.remove(r.solver)   # no wait: its stream follows this chunk
+                        resident.remove(r)
+                        used_tiles -= r.tiles
+                        finishing.append(r)
+            # read the runs that finished in the previous chunk while the
+            # device works on this one (all of them if nothing is queued)
+            collect(earlier)
             if not resident:
-                if pending:
+                collect(finishing)
+                finishing = []
+                if pending and not resident:
                     wait = pending[0].arrival * time_scale - now()
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
-                continue
-            # Enqueue the next chunk without waiting for the device: the host
-            # knows every run's progress, and the stream orders the work (a
-            # batch waits for earlier work on the stream and the stream for
-            # the batch).  The host waits only when a run completes.
-            n = min(self.chunk, min(r.remaining for r in resident))
-            if self.mode == "streams" or len(resident) == 1:
-                # each run's own launches, on its own stream
-                if batch is not None:
-                    batch.close()
-                    batch = None
-                for r in resident:
-                    r.solver.advance(n)
-            else:
-                if changed or batch is None:
-                    if batch is not None:
-                        batch.close()
-                    batch = B.Batch([r.solver for r in resident])
-                batch.advance(n)
-            chunks += 1
-            point_stages += sum(r.points for r in resident) * 5.0 * n
-            done = []
-            for r in resident:
-                r.remaining -= n
-                if r.remaining == 0:
-                    done.append(r)
-            if done:
-                if batch is not None:
-                    batch.close()
-                    batch = None
-                for r in done:
-                    if r.stream is not None:
-                        r.stream.synchronize()
-                    else:
-                        torch.cuda.synchronize()
-                t_done = now()
-                for r in done:
-                    try:
-                        out = r.solver.get_state() if self.keep_results else None
-                        r.solver.residual_norms()
-                    except B.JzError:
-                        r.ok = False
-                        failed += 1
-                        out = None
-                    r.result = out
-                    r.finished = t_done
-                    r.solver.close()
-                    r.solver = None
-                    used -= r.footprint
-                    used_tiles -= r.tiles
-                    resident.remove(r)
+        gpu_step_s = None
         if batch is not None:
+            batch.synchronize()
+            gpu_step_s = batch.timing()[0] / 1e3
             batch.close()
         torch.cuda.synchronize()
         wall = now()
         ok = [r for r in runs if r.ok]
+        extra = {"host_upload_s": upload_s, "host_collect_s": collect_s}
+        if gpu_step_s is not None:
+            extra["gpu_step_s"] = gpu_step_s   # the batch's steps, timed by events on its stream
         return ServeStats(len(ok), wall, [r.latency for r in ok], point_stages, max_res, max_bytes, chunks,
-                          failed)
+                          failed, extra)
 
 
 def run_alone(run: Run, precision: int, tile, keep_result: bool = False):
-    """The run by itself on an otherwise idle GPU: (seconds, final state)."""
+    """The run by itself on an otherwise idle GPU, with the library's launch
+    shape for its size (chunks short enough to fill the device): (seconds
+    from the upload of its payload to its result, final state)."""
     import torch
     torch.cuda.synchronize()
     t = time.perf_counter()
