@@ -487,73 +487,3 @@ def arrival_stream(seed: int = 5, nruns: int = 300, rate: float = 20.0,
     re = 10.0 ** rng.uniform(5.0, 6.0, size=nruns)
     return [dict(arrival=float(t[r]), dims=(int(n[r]),) * 3, mach=float(mach[r]),
                  re_d=float(re[r]), steps=steps, seed=seed * 100000 + r) for r in range(nruns)]
-
-
-# ----------------------------------------------------------------------------
-# the same jet box built directly in device memory (torch), for request setup
-# ----------------------------------------------------------------------------
-_SM_C1 = 0x9E3779B97F4A7C15
-_SM_C2 = 0xBF58476D1CE4E5B9
-_SM_C3 = 0x94D049BB133111EB
-
-
-def _i64(c: int) -> int:
-    """uint64 constant as the int64 with the same bits."""
-    return c - (1 << 64) if c >= (1 << 63) else c
-
-
-def _lsr(x, s: int):
-    """Logical right shift of int64 tensors holding uint64 bits."""
-    return (x >> s) & ((1 << (64 - s)) - 1)
-
-
-def splitmix64_torch(x):
-    """splitmix64 on int64 tensors (wrapping arithmetic, same bits as
-    ``splitmix64`` on uint64)."""
-    z = x + _i64(_SM_C1)
-    z = (z ^ _lsr(z, 30)) * _i64(_SM_C2)
-    z = (z ^ _lsr(z, 27)) * _i64(_SM_C3)
-    return z ^ _lsr(z, 31)
-
-
-def uniform01_torch(seed: int, counter):
-    key = int(splitmix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF)))
-    v = splitmix64_torch(counter + _i64(key))
-    import torch
-    return _lsr(v, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
-
-
-def jet_box_device(dims, mach: float, seed: int, device, lo=(0.0, -1.5, -1.5), size=(4.0, 3.0, 3.0),
-                   noise: float = 0.01, r0: float = 0.5, gamma: float = GAMMA):
-    """Uniform periodic box and round jet as device tensors: (metrics 10 x N,
-    state 5 x N), the same fields as ``uniform_box`` + ``jet_state`` up to the
-    last bits of the device tanh/division."""
-    import torch
-    ni, nj, nk = dims
-    n = ni * nj * nk
-    h = [size[0] / ni, size[1] / nj, size[2] / nk]
-    m = torch.zeros((10, n), dtype=torch.float64, device=device)
-    m[0] = h[1] * h[2]
-    m[4] = h[0] * h[2]
-    m[8] = h[0] * h[1]
-    m[9] = 1.0 / (h[0] * h[1] * h[2])
-    idx = torch.arange(n, dtype=torch.int64, device=device)
-    j = (idx // ni) % nj
-    k = idx // (ni * nj)
-    y = lo[1] + j.to(torch.float64) * h[1]
-    z = lo[2] + k.to(torch.float64) * h[2]
-    r = torch.sqrt(y * y + z * z)
-    theta = r0 / 20.0
-    U = 0.5 * mach * (1.0 - torch.tanh((r - r0) / (2.0 * theta)))
-    ctr = idx * 3
-    du = noise * mach * (2.0 * uniform01_torch(seed, ctr) - 1.0)
-    dv = noise * mach * (2.0 * uniform01_torch(seed, ctr + 1) - 1.0)
-    dw = noise * mach * (2.0 * uniform01_torch(seed, ctr + 2) - 1.0)
-    q = torch.empty((5, n), dtype=torch.float64, device=device)
-    u = U + du
-    q[0] = 1.0
-    q[1] = u
-    q[2] = dv
-    q[3] = dw
-    q[4] = (1.0 / gamma) / (gamma - 1.0) + 0.5 * (u * u + dv * dv + dw * dw)
-    return m, q
