@@ -619,22 +619,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       const Rl kap = (Rl)ph.kap_lam * mu + (Rl)ph.kap_turb * mut;
       const Rl mue = mu + mut;
       const Rl div23 = (Rl(2) / Rl(3)) * (gr[0][0] + gr[1][1] + gr[2][2]);
-      // Fhat^d = sum_a S^d_a (E_a - V_a), one Cartesian column a at a time
-      Rl F[3][5];
+      // Fhat^d = S^d . (E - V) for each direction d: the inviscid part through
+      // the contravariant velocity U^d = S^d . u (rho U, rho u_r U + S^d_r p,
+      // (e + p) U), the viscous part through the symmetric stress tensor and
+      // the energy column w_a = u_r tau_ra - q_a (q_a = -kappa dT/dx_a).
+      // Every multiply-add is an explicit fma and nothing else is contracted,
+      // so that each instantiation of this code (shapes, stages, the batch
+      // kernel) rounds the same way and their results stay bitwise equal.
+      Rl F[3][5], Uc[3];
+      {
+#pragma clang fp contract(off)
+        const Rl txx = mue * fma(Rl(2), gr[0][0], -div23), tyy = mue * fma(Rl(2), gr[1][1], -div23);
+        const Rl tzz = mue * fma(Rl(2), gr[2][2], -div23);
+        const Rl txy = mue * s01, txz = mue * s02, tyz = mue * s12;
+        const Rl tau[3][3] = {{txx, txy, txz}, {txy, tyy, tyz}, {txz, tyz, tzz}};
+        Rl wv[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        Rl ta[3];  // column a of the stress tensor
+        for (int a = 0; a < 3; ++a)
+          wv[a] = fma(kap, gr[3][a], fma(uu[2], tau[2][a], fma(uu[1], tau[1][a], uu[0] * tau[0][a])));
+        const Rl ep = Qg[4] + p;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) ta[r] = mue * (gr[r][a] + gr[a][r] - (r == a ? div23 : Rl(0)));
-        Rl ev[5];
-        ev[0] = Qg[0] * uu[a];
+        for (int d = 0; d < 3; ++d) {
+          const Rl sx = m[3 * d], sy = m[3 * d + 1], sz = m[3 * d + 2];
+          const Rl U = fma(sz, uu[2], fma(sy, uu[1], sx * uu[0]));
+          Uc[d] = U;
+          F[d][0] = Qg[0] * U;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) ev[1 + r] = Qg[1 + r] * uu[a] + (r == a ? p : Rl(0)) - ta[r];
-        ev[4] = (Qg[4] + p) * uu[a] - (uu[0] * ta[0] + uu[1] * ta[1] + uu[2] * ta[2] + kap * gr[3][a]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int v = 0; v < 5; ++v) F[d][v] = (a == 0) ? m[3 * d] * ev[v] : fma(m[3 * d + a], ev[v], F[d][v]);
+          for (int r = 0; r < 3; ++r) {
+            const Rl vis = fma(sz, tau[r][2], fma(sy, tau[r][1], sx * tau[r][0]));
+            F[d][1 + r] = fma(Qg[1 + r], U, fma(m[3 * d + r], p, -vis));
+          }
+          F[d][4] = fma(ep, U, -fma(sz, wv[2], fma(sy, wv[1], sx * wv[0])));
+        }
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -645,19 +661,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
       if constexpr (COMPACT && BASE == 0) {
         if (upd) update_loads();
       }
-      // spectral radii and anisotropic dissipation scales
-      Rl lam[3];
+      // Spectral radii and anisotropic dissipation scales.  With
+      // lambda^d = J L^d, L^d = |U^d| + a |S^d|, the scale
+      // sigma^d = phi^d lambda^d / J = phi^d L^d (phi depends only on ratios
+      // of the radii), so J drops out.
+      Rl lam[3];  // L^d
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
+#pragma clang fp contract(off)
         const Rl sx = m[3 * d], sy = m[3 * d + 1], sz = m[3 * d + 2];
-        lam[d] = fabs(J * (sx * uu[0] + sy * uu[1] + sz * uu[2])) + asnd * J * sqrt_pos(sx * sx + sy * sy + sz * sz);
+        lam[d] = fma(asnd, sqrt_pos(fma(sz, sz, fma(sy, sy, sx * sx))), fabs(Uc[d]));
       }
       Rl sig[3];
-      const Rl jinv = rcp_pos(J);
       if (ph.alpha_half) {
-        // phi^d lambda^d = lambda^d + sum_{e != d} sqrt(lambda^e lambda^d)
+        // phi^d L^d = L^d + sum_{e != d} sqrt(L^e L^d) = sqrt(L^d) sum_e sqrt(L^e)
         const Rl r0 = sqrt_pos(lam[0]), r1 = sqrt_pos(lam[1]), r2 = sqrt_pos(lam[2]);
-        const Rl rs = (r0 + r1 + r2) * jinv;
+        const Rl rs = r0 + r1 + r2;
         sig[0] = r0 * rs;
         sig[1] = r1 * rs;
         sig[2] = r2 * rs;
@@ -668,7 +687,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& A, const int lt) {
 #pragma unroll
           for (int e = 0; e < 3; ++e)
             if (e != d) phi += (Rl)pow((double)lam[e] / (double)lam[d], ph.tv_alpha);
-          sig[d] = phi * lam[d] * jinv;
+          sig[d] = phi * lam[d];
         }
       }
       sSx[c] = sig[0];
