@@ -282,9 +282,10 @@ def run_batch(prec_name: str, steps: int, warmup: int):
     b.close()
     for m in members:
         m.residual_norms()   # raises if a member went non-finite
-    # the same blocks one after another, same launch shape
+    # the same blocks one after another, same tile shape, each with the chunk
+    # length the library picks for its size (short enough to fill the device)
     for m in members:
-        m.set_tiling(*choice)
+        m.set_tiling(choice[0], choice[1], 0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for m in members:
@@ -348,6 +349,52 @@ def run_serve(prec_name: str, nruns: int, with_sequential: bool, mode: str = "ba
     return out
 
 
+def run_split(prec_name: str, parts, steps: int, warmup: int):
+    """The one-device domain split: the 512 x 256 x 256 stretched jet in
+    parts[0] x parts[1] sub-blocks along xi and zeta with two ghost layers,
+    halo copies after every stage; compared with the unsplit block (same
+    steps, same box).  The rate counts the block's own nodes."""
+    import torch
+    from paper_2003_09926_amd import binding as B
+    from paper_2003_09926_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    prec = B.JZ_FP64 if prec_name == "fp64" else B.JZ_FP32_FLUX
+    g, q = I.stretched_jet_case(DIMS, seed=2)
+    P = B.params_default(re_d=1.0e6, precision=prec)
+    d = B.Domain(g.dims, P, parts=parts)
+    d.set_grid_metrics(g.metrics)
+    d.set_state(q)
+    d.advance(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.advance(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d.close()
+    s = B.Solver(g.dims, P)
+    s.set_grid_metrics(g.metrics)
+    s.set_state(q)
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.advance(steps)
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t1
+    s.close()
+    value = g.n * 5 * steps / el
+    return {
+        "metric": "point-stage updates/s", "value": value, "unit": "point-stage updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": el * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == B.JZ_FP64 else "f32 (fluxes) + f64 (accumulation, J, norms)",
+        "data": "synthetic",
+        "config": {"workload": f"jet_512x256x256_stretched_split_{parts[0]}x{parts[1]}_{prec_name}",
+                   "parts_xi_zeta": list(parts), "ghost_layers": 2, "form": f"split-{prec_name}"},
+        "unsplit": {"value": g.n * 5 * steps / el1, "ms_per_step": el1 * 1e3 / steps},
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,16 +402,18 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", default="fp64",
                     choices=["fp64", "fp32", "domain-fp64", "domain-fp32", "cylinder-fp64", "cylinder-fp32",
-                             "batch-fp64", "batch-fp32", "serve-fp64", "serve-fp32"],
+                             "batch-fp64", "batch-fp32", "serve-fp64", "serve-fp32", "split-fp64", "split-fp32"],
                     help="fp64: FP64 path (default); fp32: FP32-flux form on the same workload; "
                          "domain-*: bounded jet domain with inflow and far-field faces; "
                          "cylinder-*: cylindrical jet mesh with the centreline; "
-                         "batch-*: 64 uneven blocks in one persistent launch per stage")
+                         "batch-*: 64 uneven blocks in one persistent launch per stage; "
+                         "serve-*: the served arrival stream; split-*: the block split into sub-blocks")
     ap.add_argument("--no-error", action="store_true", help="fp32 form: skip the error-vs-oracle run")
     ap.add_argument("--runs", type=int, default=100, help="serve forms: length of the arrival stream")
     ap.add_argument("--no-sequential", action="store_true", help="serve forms: skip the alone baseline")
     ap.add_argument("--serve-mode", default="batch", choices=["streams", "batch"],
                     help="serve forms: one batch over the resident runs, or each run on its own stream")
+    ap.add_argument("--parts", default="2,2", help="split forms: parts along xi and zeta")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true",
                     help="fp64 form: skip the FP32-flux form timed on the same workload")
@@ -393,6 +442,8 @@ def main(argv=None):
         out = run_batch(a.form.split("-")[1], a.steps, a.warmup)
     elif a.form.startswith("serve"):
         out = run_serve(a.form.split("-")[1], a.runs, not a.no_sequential, a.serve_mode)
+    elif a.form.startswith("split"):
+        out = run_split(a.form.split("-")[1], tuple(int(x) for x in a.parts.split(",")), a.steps, a.warmup)
     else:
         out = run_block(a.form, a.steps, a.warmup, with_cpu=(rank == 0 and not a.no_cpu),
                         with_error=not a.no_error, stats_interval=a.stats_interval,
