@@ -1475,16 +1475,18 @@ int jz_batch_set_graph(jz_batch* b, int enable) {
 
 int jz_batch_refresh(jz_batch* b) {
   if (!b) return fail(JZ_EINVAL, "jz_batch_refresh: NULL batch");
+  // the members' (common) tile shape, checked before anything changes
+  int bx = b->bx, by = b->by;
+  if (!b->m.empty()) {
+    bx = b->m[0]->tl.bx;
+    by = b->m[0]->tl.by;
+  }
   for (jz_solver* s : b->m)
-    if (s->tl.bx != b->bx || s->tl.by != b->by) {
-      const bool ok = b->prec == JZ_FP64 ? batch64_shape_supported(s->tl.bx, s->tl.by)
-                                         : batch32_shape_supported(s->tl.bx, s->tl.by);
-      if (!ok) return fail(JZ_EINVAL, "jz_batch_refresh: tile shape has no batch kernel");
-    }
-  b->bx = b->m[0]->tl.bx;
-  b->by = b->m[0]->tl.by;
-  for (jz_solver* s : b->m)
-    if (s->tl.bx != b->bx || s->tl.by != b->by) return fail(JZ_EINVAL, "jz_batch_refresh: members differ in tile shape");
+    if (s->tl.bx != bx || s->tl.by != by) return fail(JZ_EINVAL, "jz_batch_refresh: members differ in tile shape");
+  const bool ok = b->prec == JZ_FP64 ? batch64_shape_supported(bx, by) : batch32_shape_supported(bx, by);
+  if (!ok) return fail(JZ_EINVAL, "jz_batch_refresh: tile shape has no batch kernel");
+  b->bx = bx;
+  b->by = by;
   return batch_upload(b);
 }
 
@@ -1596,6 +1598,7 @@ int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int*
                       double* best_ms) {
   if (!b) return fail(JZ_EINVAL, "jz_batch_autotune: NULL batch");
   if (trial_steps < 1) return fail(JZ_EINVAL, "jz_batch_autotune: trial_steps < 1");
+  if (b->m.empty()) return fail(JZ_ESTATE, "jz_batch_autotune: the batch has no members");
   // batch signature: precision, stage count and the sorted member shapes
   std::vector<long long> shapes;
   for (jz_solver* s : b->m) shapes.push_back(((long long)s->ni << 40) | ((long long)s->nj << 20) | s->nk);
