@@ -55,7 +55,9 @@ hipError_t launch_reset_clock(Clock* clk, int* flag, hipStream_t st);
 hipError_t launch_halo_copy(void* dst, const void* src, bool is_float, int d, const int nd[3], const int nsrc[3],
                             int dl0, int sl0, hipStream_t st);
 hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st);
-hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st);
+hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, hipStream_t st);
+hipError_t launch_halo_jobs(const HaloJob* jobs, int njobs, bool is_float, int d, long long max_count,
+                            hipStream_t st);
 hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, hipStream_t st);
 }  // namespace jz
 
@@ -1190,62 +1192,49 @@ size_t stage_off_ofs() { return align_up(sizeof(BatchCtl)); }
 size_t stage_desc_ofs(int cap) { return align_up(stage_off_ofs() + (cap + 1) * sizeof(int)); }
 size_t stage_size(int cap) { return stage_desc_ofs(cap) + cap * sizeof(BlockDesc); }
 
-int batch_tables(jz_batch* b) {
-  const int n = (int)b->m.size();
-  const int si = b->stage_next;
-  b->stage_next = (si + 1) % jz_batch::kStage;
-  HIP_TRY(hipEventSynchronize(b->ev_stage[si]));  // the buffer's previous copy is done
-  char* h = b->h_stage[si];
-  BlockDesc* d = reinterpret_cast<BlockDesc*>(h + stage_desc_ofs(b->cap));
-  int* off = reinterpret_cast<int*>(h + stage_off_ofs());
-  off[0] = 0;
-  b->npoints = 0;
-  for (int i = 0; i < n; ++i) {
-    jz_solver* s = b->m[i];
-    BlockDesc& D = d[i];
-    D.q0 = s->q0;
-    D.bufA = s->prec == JZ_FP64 ? (void*)s->qa : (void*)s->q32a;
-    D.bufB = s->prec == JZ_FP64 ? (void*)s->qb : (void*)s->q32b;
-    D.met = s->met;
-    D.jac = s->jac;
-    D.clock = s->clock;
-    D.norm_part = s->norm_part;
-    D.lam_part = s->lam_part;
-    D.flag = s->flag;
-    D.N = s->N;
-    D.ni = s->ni;
-    D.nj = s->nj;
-    D.nk = s->nk;
-    D.tiles_i = s->tl.tiles_i;
-    D.tiles_j = s->tl.tiles_j;
-    D.kchunk = s->tl.kchunk;
-    D.nchunks = s->tl.nchunks;
-    D.ntiles = s->tl.nblocks;
-    D.in = s->in;
-    D.ctl = step_ctl(s);
-    D.ph = s->ph;
-    off[i + 1] = off[i] + s->tl.nblocks;
-    b->npoints += s->N;
-  }
-  b->total = off[n];
-  // Split the tile list among the slots by plane steps: a tile of a chunk of
-  // L planes marches L + 2 of them, plus about two planes' worth of set-up and
-  // reductions.  Tiles are in each member's logical order (chunk by chunk).
-  BatchCtl& c = *reinterpret_cast<BatchCtl*>(h);
+// The descriptor of a block as the persistent stage launches read it.
+void fill_desc(jz_solver* s, BlockDesc& D) {
+  D.q0 = s->q0;
+  D.bufA = s->prec == JZ_FP64 ? (void*)s->qa : (void*)s->q32a;
+  D.bufB = s->prec == JZ_FP64 ? (void*)s->qb : (void*)s->q32b;
+  D.met = s->met;
+  D.jac = s->jac;
+  D.clock = s->clock;
+  D.norm_part = s->norm_part;
+  D.lam_part = s->lam_part;
+  D.flag = s->flag;
+  D.N = s->N;
+  D.ni = s->ni;
+  D.nj = s->nj;
+  D.nk = s->nk;
+  D.tiles_i = s->tl.tiles_i;
+  D.tiles_j = s->tl.tiles_j;
+  D.kchunk = s->tl.kchunk;
+  D.nchunks = s->tl.nchunks;
+  D.ntiles = s->tl.nblocks;
+  D.in = s->in;
+  D.ctl = step_ctl(s);
+  D.ph = s->ph;
+}
+
+// The work list of blocks m (tiles member by member, each in its logical
+// order) with zeroed counters.  The tile list is split among the slots by
+// plane steps: a tile of a chunk of L planes marches L + 2 of them, plus
+// about two planes' worth of set-up and reductions.
+void fill_worklist(const std::vector<jz_solver*>& m, BatchCtl& c) {
   std::memset(&c, 0, sizeof c);
-  c.nblk = n;
-  c.total = b->total;
+  c.nblk = (int)m.size();
   auto tile_cost = [](const jz_solver* s, int chunk) {
     const int ek = s->in.hi[2] - s->in.lo[2];
     const int len = std::min(s->tl.kchunk, ek - chunk * s->tl.kchunk);
     return (long long)len + 4;
   };
   long long all = 0;
-  for (jz_solver* s : b->m)
+  for (jz_solver* s : m)
     for (int ch = 0; ch < s->tl.nchunks; ++ch) all += tile_cost(s, ch) * s->tl.tiles_i * s->tl.tiles_j;
   int x = 1, g = 0;
   long long acc = 0;
-  for (jz_solver* s : b->m)
+  for (jz_solver* s : m)
     for (int ch = 0; ch < s->tl.nchunks; ++ch) {
       const long long w = tile_cost(s, ch);
       for (int t = 0; t < s->tl.tiles_i * s->tl.tiles_j; ++t, ++g) {
@@ -1254,6 +1243,27 @@ int batch_tables(jz_batch* b) {
       }
     }
   while (x <= kBatchSlots) c.split[x++] = g;
+  c.total = g;
+}
+
+int batch_tables(jz_batch* b) {
+  const int n = (int)b->m.size();
+  const int si = b->stage_next;
+  b->stage_next = (si + 1) % jz_batch::kStage;
+  HIP_TRY(hipEventSynchronize(b->ev_stage[si]));  // the buffer's previous copy is done
+  char* h = b->h_stage[si];
+  BlockDesc* d = reinterpret_cast<BlockDesc*>(h + stage_desc_ofs(b->cap));
+  int* off = reinterpret_cast<int*>(h + stage_off_ofs());
+  BatchCtl& c = *reinterpret_cast<BatchCtl*>(h);
+  off[0] = 0;
+  b->npoints = 0;
+  for (int i = 0; i < n; ++i) {
+    fill_desc(b->m[i], d[i]);
+    off[i + 1] = off[i] + b->m[i]->tl.nblocks;
+    b->npoints += b->m[i]->N;
+  }
+  b->total = off[n];
+  fill_worklist(b->m, c);
   if (n > 0) HIP_TRY(hipMemcpyAsync(b->d_desc, d, n * sizeof(BlockDesc), hipMemcpyHostToDevice, b->st));
   HIP_TRY(hipMemcpyAsync(b->d_off, off, (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->st));
   HIP_TRY(hipMemcpyAsync(b->d_ctl, &c, sizeof c, hipMemcpyHostToDevice, b->st));
@@ -1756,6 +1766,19 @@ struct jz_domain {
   int halo;                      // bit d: direction d is split
   long long n_interior;
   bool dt_valid;
+  // One persistent launch per stage over the tiles of all parts (FP64, when
+  // the parts' tile shape has a batch kernel), and one launch per exchange pass:
+  // the parts' descriptors, tile offsets and work list, and the ghost
+  // refills of each pass (xi, zeta) for the stage outputs of each kind
+  // (0: buffer A, 1: buffer B, 2: Q(0)), stored one after another.
+  bool batched;
+  int bx, by;
+  BlockDesc* d_desc;
+  int* d_off;
+  BatchCtl* d_ctl;
+  HaloJob* d_jobs;
+  int job_off[3][2], njobs[3][2];
+  long long job_max[3][2];
 };
 
 namespace {
@@ -1802,11 +1825,24 @@ void* dom_stage_out(jz_solver* s, int k, int ns) {
   return (k % 2 == 0) ? (f32 ? (void*)s->q32a : (void*)s->qa) : (f32 ? (void*)s->q32b : (void*)s->qb);
 }
 
+// kind of the stage output of stage k: 0 buffer A, 1 buffer B, 2 Q(0)
+int dom_kind(int k, int ns) { return k == ns - 1 ? 2 : (k % 2); }
+
 // Refill the ghost layers of every part's buffer of stage k: first along xi
 // (all zeta planes), then along zeta over the whole padded width, which
 // carries the xi ghost columns -- and with them the corners -- across.
 int dom_exchange(jz_domain* D, int k, int ns) {
   const bool f32 = D->p.precision == JZ_FP32_FLUX && k != ns - 1;
+  if (D->d_jobs) {
+    const int kind = dom_kind(k, ns);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int d = pass == 0 ? 0 : 2;
+      if (!((D->halo >> d) & 1)) continue;
+      HIP_TRY(launch_halo_jobs(D->d_jobs + D->job_off[kind][pass], D->njobs[kind][pass], f32, d,
+                               D->job_max[kind][pass], D->stream));
+    }
+    return JZ_OK;
+  }
   for (int d = 0; d < 3; d += 2) {
     if (!((D->halo >> d) & 1)) continue;
     for (int c = 0; c < D->parts[2]; ++c)
@@ -1827,6 +1863,85 @@ int dom_exchange(jz_domain* D, int k, int ns) {
                                  2, D->stream));
       }
   }
+  return JZ_OK;
+}
+
+// The ghost refills of every pass and stage-output kind, and, when the
+// parts' tile shape has a batch kernel, their batch tables.
+int dom_build_launch_tables(jz_domain* D) {
+  std::vector<HaloJob> jobs;
+  for (int kind = 0; kind < 3; ++kind)
+    for (int pass = 0; pass < 2; ++pass) {
+      const int d = pass == 0 ? 0 : 2;
+      D->job_off[kind][pass] = (int)jobs.size();
+      D->njobs[kind][pass] = 0;
+      D->job_max[kind][pass] = 0;
+      if (!((D->halo >> d) & 1)) continue;
+      for (int c = 0; c < D->parts[2]; ++c)
+        for (int a = 0; a < D->parts[0]; ++a) {
+          jz_solver* dst = D->sub[dom_index(D, a, c)];
+          const int np = D->parts[d], pos = d == 0 ? a : c;
+          const int prev = (pos + np - 1) % np, next = (pos + 1) % np;
+          jz_solver* lo = D->sub[d == 0 ? dom_index(D, prev, c) : dom_index(D, a, prev)];
+          jz_solver* hi = D->sub[d == 0 ? dom_index(D, next, c) : dom_index(D, a, next)];
+          auto buf = [&](jz_solver* s) -> void* {
+            const bool f32 = s->prec == JZ_FP32_FLUX;
+            if (kind == 2) return s->q0;
+            return kind == 0 ? (f32 ? (void*)s->q32a : (void*)s->qa) : (f32 ? (void*)s->q32b : (void*)s->qb);
+          };
+          for (int side = 0; side < 2; ++side) {
+            jz_solver* src = side == 0 ? lo : hi;
+            HaloJob J;
+            J.dst = buf(dst);
+            J.src = buf(src);
+            J.nd[0] = dst->ni;
+            J.nd[1] = dst->nj;
+            J.nd[2] = dst->nk;
+            J.nsrc[0] = src->ni;
+            J.nsrc[1] = src->nj;
+            J.nsrc[2] = src->nk;
+            // low ghosts <- the last two own layers of the lower part; high
+            // ghosts <- the first two own layers of the upper part
+            J.dl0 = side == 0 ? 0 : J.nd[d] - 2;
+            J.sl0 = side == 0 ? J.nsrc[d] - 4 : 2;
+            jobs.push_back(J);
+            const long long cnt = 2LL * J.nd[face_e(d)] * J.nd[face_f(d)] * 5;
+            if (cnt > D->job_max[kind][pass]) D->job_max[kind][pass] = cnt;
+            D->njobs[kind][pass] += 1;
+          }
+        }
+    }
+  if (!jobs.empty()) {
+    HIP_TRY(hipMalloc((void**)&D->d_jobs, jobs.size() * sizeof(HaloJob)));
+    HIP_TRY(hipMemcpy(D->d_jobs, jobs.data(), jobs.size() * sizeof(HaloJob), hipMemcpyHostToDevice));
+  }
+  // Batched stage launches (FP64): every part shares the tile shape.  The
+  // FP32-flux batch kernel keeps the primitive ring and reads the metrics
+  // again in its first and last stages, which costs more than the tails of
+  // one launch per part (split 2 x 2 at 512 x 256 x 256: 11 % against 10 %
+  // over the unsplit block); in FP64 the batched launch took the overhead
+  // from 13 % to 6 %.
+  D->bx = D->sub[0]->tl.bx;
+  D->by = D->sub[0]->tl.by;
+  bool same = true;
+  for (jz_solver* s : D->sub) same = same && s->tl.bx == D->bx && s->tl.by == D->by;
+  D->batched = same && D->p.precision == JZ_FP64 && batch64_shape_supported(D->bx, D->by);
+  if (!D->batched) return JZ_OK;
+  const int n = (int)D->sub.size();
+  std::vector<BlockDesc> desc(n);
+  std::vector<int> off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    fill_desc(D->sub[i], desc[i]);
+    off[i + 1] = off[i] + D->sub[i]->tl.nblocks;
+  }
+  BatchCtl c;
+  fill_worklist(D->sub, c);
+  HIP_TRY(hipMalloc((void**)&D->d_desc, n * sizeof(BlockDesc)));
+  HIP_TRY(hipMalloc((void**)&D->d_off, (n + 1) * sizeof(int)));
+  HIP_TRY(hipMalloc((void**)&D->d_ctl, sizeof(BatchCtl)));
+  HIP_TRY(hipMemcpy(D->d_desc, desc.data(), n * sizeof(BlockDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(D->d_off, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(D->d_ctl, &c, sizeof c, hipMemcpyHostToDevice));
   return JZ_OK;
 }
 
@@ -1896,6 +2011,12 @@ int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, in
   D->d_sub = nullptr;
   D->n_interior = (long long)ni * nj * nk;
   D->dt_valid = false;
+  D->batched = false;
+  D->bx = D->by = 0;
+  D->d_desc = nullptr;
+  D->d_off = nullptr;
+  D->d_ctl = nullptr;
+  D->d_jobs = nullptr;
   // balanced parts: sizes differ by at most one node, larger ones first
   for (int d = 0; d < 3; ++d) {
     const int np = D->parts[d];
@@ -1935,6 +2056,7 @@ int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, in
     return fail(JZ_ENOMEM, "jz_domain_create: %s", hipGetErrorString(e));
   }
   int rc = dom_upload_table(D);
+  if (rc == JZ_OK) rc = dom_build_launch_tables(D);
   if (rc) {
     jz_domain_destroy(D);
     return rc;
@@ -1979,15 +2101,22 @@ int jz_domain_advance(jz_domain* D, int nsteps) {
   const int ns = D->p.n_stages;
   for (int step = 0; step < nsteps; ++step) {
     for (int k = 0; k < ns; ++k) {
-      for (jz_solver* s : D->sub) {
-        const void* in = k == 0 ? (const void*)s->q0 : dom_stage_out(s, k - 1, ns);
-        StageArgs a = stage_args(s, in, dom_stage_out(s, k, ns), s->p.rk_alpha[k]);
-        HIP_TRY(launch_stage(s, a, k, ns, false));
+      if (D->batched) {
+        // one persistent launch over the tiles of every part
+        const double alpha = D->p.rk_alpha[k];
+        HIP_TRY(launch_stage_batch_fp64(D->d_desc, D->d_off, D->d_ctl, k, ns, alpha, D->bx, D->by, D->stream));
+      } else {
+        for (jz_solver* s : D->sub) {
+          const void* in = k == 0 ? (const void*)s->q0 : dom_stage_out(s, k - 1, ns);
+          StageArgs a = stage_args(s, in, dom_stage_out(s, k, ns), s->p.rk_alpha[k]);
+          HIP_TRY(launch_stage(s, a, k, ns, false));
+        }
       }
       rc = dom_exchange(D, k, ns);
       if (rc) return rc;
     }
-    HIP_TRY(launch_domain_finalize(D->d_sub, (int)D->sub.size(), dom_ctl(D), D->stream));
+    HIP_TRY(launch_domain_finalize(D->d_sub, (int)D->sub.size(), dom_ctl(D), D->batched ? D->d_ctl : nullptr,
+                                   D->stream));
   }
   return JZ_OK;
 }
@@ -2025,6 +2154,10 @@ int jz_domain_destroy(jz_domain* D) {
   if (D->stream) (void)hipStreamSynchronize(D->stream);
   for (jz_solver* s : D->sub) jz_destroy(s);
   if (D->d_sub) (void)hipFree(D->d_sub);
+  if (D->d_desc) (void)hipFree(D->d_desc);
+  if (D->d_off) (void)hipFree(D->d_off);
+  if (D->d_ctl) (void)hipFree(D->d_ctl);
+  if (D->d_jobs) (void)hipFree(D->d_jobs);
   delete D;
   return JZ_OK;
 }

@@ -561,6 +561,41 @@ __global__ __launch_bounds__(256) void halo_copy_kernel(T* __restrict__ dst, con
   dst[5 * id + v] = src[5 * is + v];
 }
 
+// Every ghost refill of one exchange pass in one launch: workgroup row y
+// serves job y (rows beyond a job's size return at once).
+template <typename T>
+__global__ __launch_bounds__(256) void halo_jobs_kernel(const HaloJob* __restrict__ jobs, int d) {
+  const HaloJob& J = jobs[blockIdx.y];
+  const int e = face_e(d), f = face_f(d);
+  const long long count = 2LL * J.nd[e] * J.nd[f] * 5;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int v = (int)(t % 5);
+  const long long node = t / 5;
+  const long long face = (long long)J.nd[e] * J.nd[f];
+  const int layer = (int)(node / face);
+  const long long r = node % face;
+  int c[3];
+  c[e] = (int)(r % J.nd[e]);
+  c[f] = (int)(r / J.nd[e]);
+  c[d] = J.dl0 + layer;
+  const long long id = c[0] + (long long)J.nd[0] * (c[1] + (long long)J.nd[1] * c[2]);
+  c[d] = J.sl0 + layer;
+  const long long is = c[0] + (long long)J.nsrc[0] * (c[1] + (long long)J.nsrc[1] * c[2]);
+  static_cast<T*>(J.dst)[5 * id + v] = static_cast<const T*>(J.src)[5 * is + v];
+}
+
+hipError_t launch_halo_jobs(const HaloJob* jobs, int njobs, bool is_float, int d, long long max_count,
+                            hipStream_t st) {
+  if (njobs < 1) return hipSuccess;
+  const dim3 grid((unsigned)((max_count + 255) / 256), (unsigned)njobs);
+  if (is_float)
+    hipLaunchKernelGGL(halo_jobs_kernel<float>, grid, dim3(256), 0, st, jobs, d);
+  else
+    hipLaunchKernelGGL(halo_jobs_kernel<double>, grid, dim3(256), 0, st, jobs, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_halo_copy(void* dst, const void* src, bool is_float, int d, const int nd[3], const int nsrc[3],
                             int dl0, int sl0, hipStream_t st) {
   const int e = face_e(d), f = face_f(d);
@@ -598,8 +633,10 @@ __global__ __launch_bounds__(FIN_T) void domain_dt_kernel(const DomainSub* __res
 // just used, and the next dt from the last stage's lambda maxima of all
 // sub-blocks -- the same values in every sub-block's clock.
 __global__ __launch_bounds__(FIN_T) void domain_finalize_kernel(const DomainSub* __restrict__ sub, int P,
-                                                                StepCtl ctl) {
+                                                                StepCtl ctl, BatchCtl* __restrict__ work) {
   __shared__ double red[FIN_T];
+  // the tile counters of the batched stage launches, for the next step
+  if (work && threadIdx.x < 5 * kBatchSlots) (&work->next[0][0])[threadIdx.x] = 0;
   for (int p = 0; p < P; ++p)
     if (*sub[p].flag) return;  // a failed step froze the state
   double sums[5] = {0, 0, 0, 0, 0}, maxs[5] = {0, 0, 0, 0, 0}, lmax = 0.0;
@@ -635,8 +672,8 @@ hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st) {
-  hipLaunchKernelGGL(domain_finalize_kernel, dim3(1), dim3(FIN_T), 0, st, sub, P, ctl);
+hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, hipStream_t st) {
+  hipLaunchKernelGGL(domain_finalize_kernel, dim3(1), dim3(FIN_T), 0, st, sub, P, ctl, work);
   return hipGetLastError();
 }
 

@@ -122,6 +122,16 @@ struct BatchCtl {
   int next[5][kBatchSlots];
 };
 
+// One ghost refill of a domain part along direction d: layers [dl0, dl0 + 2)
+// of dst take layers [sl0, sl0 + 2) of src, over the whole extent of dst in
+// the other two directions (the same as src's); five values per node.
+struct HaloJob {
+  void* dst;
+  const void* src;
+  int nd[3], nsrc[3];
+  int dl0, sl0;
+};
+
 // One sub-block of a domain, for the fixed-order reductions over all of them.
 struct DomainSub {
   Clock* clock;
