@@ -52,8 +52,6 @@ hipError_t launch_finalize_dt(Clock* clk, const double* lam_part, int nb, StepCt
 hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const double* lam_part, int nb, StepCtl ctl,
                                 int* flag, hipStream_t st);
 hipError_t launch_reset_clock(Clock* clk, int* flag, hipStream_t st);
-hipError_t launch_halo_copy(void* dst, const void* src, bool is_float, int d, const int nd[3], const int nsrc[3],
-                            int dl0, int sl0, hipStream_t st);
 hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st);
 hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, hipStream_t st);
 hipError_t launch_halo_jobs(const HaloJob* jobs, int njobs, bool is_float, int d, long long max_count,
@@ -1830,38 +1828,16 @@ int dom_kind(int k, int ns) { return k == ns - 1 ? 2 : (k % 2); }
 
 // Refill the ghost layers of every part's buffer of stage k: first along xi
 // (all zeta planes), then along zeta over the whole padded width, which
-// carries the xi ghost columns -- and with them the corners -- across.
+// carries the xi ghost columns -- and with them the corners -- across.  One
+// launch per split direction over that pass's table of copy jobs.
 int dom_exchange(jz_domain* D, int k, int ns) {
   const bool f32 = D->p.precision == JZ_FP32_FLUX && k != ns - 1;
-  if (D->d_jobs) {
-    const int kind = dom_kind(k, ns);
-    for (int pass = 0; pass < 2; ++pass) {
-      const int d = pass == 0 ? 0 : 2;
-      if (!((D->halo >> d) & 1)) continue;
-      HIP_TRY(launch_halo_jobs(D->d_jobs + D->job_off[kind][pass], D->njobs[kind][pass], f32, d,
-                               D->job_max[kind][pass], D->stream));
-    }
-    return JZ_OK;
-  }
-  for (int d = 0; d < 3; d += 2) {
+  const int kind = dom_kind(k, ns);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int d = pass == 0 ? 0 : 2;
     if (!((D->halo >> d) & 1)) continue;
-    for (int c = 0; c < D->parts[2]; ++c)
-      for (int a = 0; a < D->parts[0]; ++a) {
-        jz_solver* dst = D->sub[dom_index(D, a, c)];
-        // the neighbouring parts along d (periodic: the first and last are neighbours)
-        const int np = D->parts[d], pos = d == 0 ? a : c;
-        const int prev = (pos + np - 1) % np, next = (pos + 1) % np;
-        jz_solver* lo = D->sub[d == 0 ? dom_index(D, prev, c) : dom_index(D, a, prev)];
-        jz_solver* hi = D->sub[d == 0 ? dom_index(D, next, c) : dom_index(D, a, next)];
-        const int nd[3] = {dst->ni, dst->nj, dst->nk};
-        const int nl[3] = {lo->ni, lo->nj, lo->nk}, nh[3] = {hi->ni, hi->nj, hi->nk};
-        // ghost layers 0, 1 <- the last two interior layers of the lower neighbour;
-        // n-2, n-1 <- its upper neighbour's first two
-        HIP_TRY(launch_halo_copy(dom_stage_out(dst, k, ns), dom_stage_out(lo, k, ns), f32, d, nd, nl, 0,
-                                 nl[d] - 4, D->stream));
-        HIP_TRY(launch_halo_copy(dom_stage_out(dst, k, ns), dom_stage_out(hi, k, ns), f32, d, nd, nh, nd[d] - 2,
-                                 2, D->stream));
-      }
+    HIP_TRY(launch_halo_jobs(D->d_jobs + D->job_off[kind][pass], D->njobs[kind][pass], f32, d,
+                             D->job_max[kind][pass], D->stream));
   }
   return JZ_OK;
 }

@@ -538,29 +538,6 @@ hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, h
 // Two node layers of direction d, all positions across it: dst layers dl0,
 // dl0 + 1 <- src layers sl0, sl0 + 1 (node-major, 5 values per node).  The
 // two blocks have the same extents across d.
-template <typename T>
-__global__ __launch_bounds__(256) void halo_copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int d, int n0d,
-                                                        int n1d, int n2d, int n0s, int n1s, int dl0, int sl0,
-                                                        long long count) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const int v = (int)(t % 5);
-  const long long node = t / 5;
-  const int nd[3] = {n0d, n1d, n2d};
-  const int e = face_e(d), f = face_f(d);
-  const long long face = (long long)nd[e] * nd[f];
-  const int layer = (int)(node / face);
-  const long long r = node % face;
-  int c[3];
-  c[e] = (int)(r % nd[e]);
-  c[f] = (int)(r / nd[e]);
-  c[d] = dl0 + layer;
-  const long long id = c[0] + (long long)n0d * (c[1] + (long long)n1d * c[2]);
-  c[d] = sl0 + layer;
-  const long long is = c[0] + (long long)n0s * (c[1] + (long long)n1s * c[2]);
-  dst[5 * id + v] = src[5 * is + v];
-}
-
 // Every ghost refill of one exchange pass in one launch: workgroup row y
 // serves job y (rows beyond a job's size return at once).
 template <typename T>
@@ -593,20 +570,6 @@ hipError_t launch_halo_jobs(const HaloJob* jobs, int njobs, bool is_float, int d
     hipLaunchKernelGGL(halo_jobs_kernel<float>, grid, dim3(256), 0, st, jobs, d);
   else
     hipLaunchKernelGGL(halo_jobs_kernel<double>, grid, dim3(256), 0, st, jobs, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_halo_copy(void* dst, const void* src, bool is_float, int d, const int nd[3], const int nsrc[3],
-                            int dl0, int sl0, hipStream_t st) {
-  const int e = face_e(d), f = face_f(d);
-  const long long count = 2LL * nd[e] * nd[f] * 5;
-  const long long blocks = (count + 255) / 256;
-  if (is_float)
-    hipLaunchKernelGGL(halo_copy_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, (float*)dst,
-                       (const float*)src, d, nd[0], nd[1], nd[2], nsrc[0], nsrc[1], dl0, sl0, count);
-  else
-    hipLaunchKernelGGL(halo_copy_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, (double*)dst,
-                       (const double*)src, d, nd[0], nd[1], nd[2], nsrc[0], nsrc[1], dl0, sl0, count);
   return hipGetLastError();
 }
 
