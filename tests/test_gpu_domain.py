@@ -69,6 +69,17 @@ def test_odd_size_split_bitwise(B, odd_case, parts, prec):
     np.testing.assert_allclose(ns[0], nu[0], rtol=1e-12, atol=0)
 
 
+def test_split_without_batch_kernel_shape(B, odd_case):
+    """A tile shape with no batch kernel (12 x 28 tiles) advances the parts
+    one launch each instead of in one batched launch: still bitwise equal."""
+    dims, m, q = odd_case
+    _log(f"domain {dims} parts (2, 2) fp64 tiles 12x28 (one launch per part)")
+    prm = B.params_default(re_d=2.0e3, tile_i=12, tile_j=28)
+    qu, cu, _ = _unsplit(B, dims, prm, m, q, 2)
+    qs, cs, _ = _split(B, dims, prm, m, q, 2, (2, 2))
+    assert np.array_equal(qu, qs) and cu == cs
+
+
 def test_odd_size_split_matches_oracle(B, odd_case):
     dims, m, q = odd_case
     _log(f"domain {dims} parts (2, 2) vs oracle")
