@@ -243,8 +243,9 @@ int jz_destroy(jz_solver* s);
  * (FP64: 16x12, 32x8, 16x16, 28x12, 12x12; FP32-flux: 32x16, 28x20, 28x12, 12x12), and must have their
  * grid and state set.  Each member's results are bitwise those of the member
  * advanced alone with the same tile shape.  Members need n_stages >= 2 (JZ_EINVAL
- * otherwise).  The caller keeps ownership of the
- * members and must not advance them on their own while the batch is in use.
+ * otherwise).  The caller keeps ownership of the members, must not advance
+ * them on their own while they belong to the batch, and must take a member
+ * out (jz_batch_remove) or destroy the batch before destroying the member.
  * hip_stream orders the batch against the caller's work (NULL = null
  * stream); the batch runs on an internal non-blocking stream. */
 typedef struct jz_batch jz_batch;
