@@ -32,25 +32,6 @@ struct CoordView {
     v += floor_div(c[2], n[2]) * P.p[6 + a];
     return v;
   }
-  // difference of the node function g along d at logical node c: centred,
-  // or one-sided at the two end nodes of a bounded direction
-  template <class G>
-  __device__ double diff(const G& g, const int c[3], int d) const {
-    int p[3] = {c[0], c[1], c[2]}, m[3] = {c[0], c[1], c[2]};
-    if ((bnd >> d) & 1) {
-      if (c[d] == 0) {
-        p[d] += 1;
-        return g(p) - g(c);
-      }
-      if (c[d] == n[d] - 1) {
-        m[d] -= 1;
-        return g(c) - g(m);
-      }
-    }
-    p[d] += 1;
-    m[d] -= 1;
-    return 0.5 * (g(p) - g(m));
-  }
 };
 
 }  // namespace
@@ -59,10 +40,15 @@ struct CoordView {
 // and (a, a1, a2),  S^d_a = delta_d2(X_a2 delta_d1 X_a1) - delta_d1(X_a2 delta_d2 X_a1),
 // with X_a2 measured from the centre node; J = 1 / det(delta_d X_a).  Because
 // the centred differences commute, sum_d delta_d S^d_a vanishes identically,
-// which keeps a uniform flow exactly steady on any grid.  Along a bounded
-// direction the differences at its two end nodes are one-sided; they enter
-// only the metrics of the outermost boundary layer (the far-field normal),
-// never the residual of an advanced node.
+// which keeps a uniform flow exactly steady on any grid.
+//
+// Each thread loads the unwrapped coordinates of the 19 nodes the formula
+// reaches (the centre, its 6 face and 12 edge neighbours: offsets with at
+// most two nonzero components) once, and applies every difference as a
+// weighted sum over offsets -1, 0, +1: weights (-1/2, 0, 1/2) inside, and
+// along a bounded direction (0, -1, 1) at its first node and (-1, 1, 0) at
+// its last (one-sided; they enter only the metrics of the outermost boundary
+// layer, i.e. the far-field normal, never the residual of an advanced node).
 // MET32 = false: 10 doubles per node; true: 9 floats per node + J in double.
 template <bool MET32>
 __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, void* __restrict__ mout,
@@ -71,31 +57,55 @@ __global__ __launch_bounds__(256) void metrics_tl_kernel(CoordView cv, void* __r
   float* m32 = (float*)mout;
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= cv.N) return;
-  const int i = (int)(n % cv.n[0]);
-  const int j = (int)((n / cv.n[0]) % cv.n[1]);
-  const int k = (int)(n / ((long long)cv.n[0] * cv.n[1]));
-  const int c[3] = {i, j, k};
+  const int c[3] = {(int)(n % cv.n[0]), (int)((n / cv.n[0]) % cv.n[1]), (int)(n / ((long long)cv.n[0] * cv.n[1]))};
+  // coordinates of the neighbourhood: nb[a][o0 + 3 (o1 + 3 o2) + 13] for offset (o0, o1, o2)
+  double nb[3][27];
+  for (int o = 0; o < 27; ++o) {
+    const int off[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+    if (off[0] != 0 && off[1] != 0 && off[2] != 0) continue;  // corners: never reached
+    const int e[3] = {c[0] + off[0], c[1] + off[1], c[2] + off[2]};
+    for (int a = 0; a < 3; ++a) nb[a][o] = cv.at(a, e);
+  }
+  // difference weights along each direction at this node, for offsets -1, 0, +1
+  double w[3][3];
+  for (int d = 0; d < 3; ++d) {
+    const bool b = (cv.bnd >> d) & 1;
+    const bool first = b && c[d] == 0, last = b && c[d] == cv.n[d] - 1;
+    w[d][0] = first ? 0.0 : (last ? -1.0 : -0.5);
+    w[d][1] = first ? -1.0 : (last ? 1.0 : 0.0);
+    w[d][2] = first ? 1.0 : (last ? 0.0 : 0.5);
+  }
+  const int stride[3] = {1, 3, 9};
+  // difference along d of coordinate a around the node at offset index o
+  auto delta = [&](int a, int d, int o) {
+    return (w[d][0] * nb[a][o - stride[d]] + w[d][1] * nb[a][o]) + w[d][2] * nb[a][o + stride[d]];
+  };
+  const int oc = 13;  // the centre
   for (int d = 0; d < 3; ++d) {
     const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
     for (int a = 0; a < 3; ++a) {
       const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
-      const double xc = cv.at(a2, c);
-      auto xa1 = [&](const int* e) { return cv.at(a1, e); };
-      // X_a2 delta_d1 X_a1 and X_a2 delta_d2 X_a1, X_a2 from the centre node
-      auto h1 = [&](const int* e) { return (cv.at(a2, e) - xc) * cv.diff(xa1, e, d1); };
-      auto h2 = [&](const int* e) { return (cv.at(a2, e) - xc) * cv.diff(xa1, e, d2); };
-      const double sda = cv.diff(h1, c, d2) - cv.diff(h2, c, d1);
+      // outer difference along p of (X_a2 - X_a2(centre)) times the inner
+      // difference of X_a1 along q, taken at the nodes o = centre + s e_p
+      auto term = [&](int p, int q) {
+        double acc = 0.0;
+        for (int s = -1; s <= 1; ++s) {
+          const int o = oc + s * stride[p];
+          acc += w[p][s + 1] * ((nb[a2][o] - nb[a2][oc]) * delta(a1, q, o));
+        }
+        return acc;
+      };
+      const double sda = term(d2, d1) - term(d1, d2);
       if (MET32)
         m32[9 * n + 3 * d + a] = (float)sda;
       else
         m[10 * n + 3 * d + a] = sda;
     }
   }
+  // J = 1 / det(dX_a / dxi_d), the determinant expanded along its first row
   double M[3][3];
-  for (int a = 0; a < 3; ++a) {
-    auto xa = [&](const int* e) { return cv.at(a, e); };
-    for (int d = 0; d < 3; ++d) M[a][d] = cv.diff(xa, c, d);
-  }
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) M[a][d] = delta(a, d, oc);
   const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
                      M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
                      M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);

@@ -24,46 +24,60 @@ struct BcArgs {
 };
 
 // Far-field state from the one-dimensional characteristics normal to the face
-// (outward unit normal nh).  The outgoing invariant u_n + 2a/(gamma-1) is
-// taken from the interior state qi, the incoming u_n - 2a/(gamma-1) from the
-// free stream (rho = 1, u = (mach_inf, 0, 0), p = 1/gamma, a = 1); their sum
-// and difference give u_n and a at the face.  Entropy p/rho^gamma and the
-// tangential velocity come from the upwind side.  If the interior normal
-// velocity is supersonic, the upwind side supplies everything.
+// (outward unit normal nh).  Along the normal, u_n + 2a/(gamma-1) travels out
+// of the block and u_n - 2a/(gamma-1) into it: the face takes the first from
+// the interior state qi and the second from the free stream (rho = 1,
+// u = (mach_inf, 0, 0), p = 1/gamma, a = 1), which fixes u_n and a there.
+// The other two characteristic quantities, entropy and tangential velocity,
+// are carried by the flow: the face takes them from the side the flow comes
+// from (the "upwind state" w).  With the entropy of w, rho a^(2/(1-gamma)) is
+// constant along the isentrope, so the face density is rho_w (a_b / a_w)^(2 /
+// (gamma - 1)).  A supersonic normal flow carries all five quantities from
+// its upwind side, whose conserved state the face then takes as it is.
 __device__ void farfield_state(double g, double mach_inf, const double qi[5], const double nh[3], double qb[5]) {
-  const double ri = qi[0];
-  const double ui[3] = {qi[1] / ri, qi[2] / ri, qi[3] / ri};
-  const double pi = (g - 1.0) * (qi[4] - 0.5 * ri * (ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2]));
-  const double ai = sqrt(g * pi / ri);
-  const double re = 1.0, pe = 1.0 / g, ae = 1.0;
-  const double ue[3] = {mach_inf, 0.0, 0.0};
-  const double uni = ui[0] * nh[0] + ui[1] * nh[1] + ui[2] * nh[2];
-  const double une = ue[0] * nh[0] + ue[1] * nh[1] + ue[2] * nh[2];
-  double rb, pb, ub[3];
-  if (uni >= ai) {
-    rb = ri;
-    pb = pi;
-    for (int a = 0; a < 3; ++a) ub[a] = ui[a];
-  } else if (uni <= -ai) {
-    rb = re;
-    pb = pe;
-    for (int a = 0; a < 3; ++a) ub[a] = ue[a];
-  } else {
-    const double rp = uni + 2.0 * ai / (g - 1.0);
-    const double rm = une - 2.0 * ae / (g - 1.0);
-    const double unb = 0.5 * (rp + rm);
-    const double ab = 0.25 * (g - 1.0) * (rp - rm);
-    const bool out = unb > 0.0;
-    const double ent = out ? pi / pow(ri, g) : pe / pow(re, g);
-    const double* ut = out ? ui : ue;
-    const double unt = out ? uni : une;
-    for (int a = 0; a < 3; ++a) ub[a] = ut[a] + (unb - unt) * nh[a];
-    rb = pow(ab * ab / (g * ent), 1.0 / (g - 1.0));
-    pb = rb * ab * ab / g;
+  const double gm1 = g - 1.0;
+  // interior primitives
+  const double rinv = 1.0 / qi[0];
+  double vi[3], ke_i = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    vi[a] = qi[1 + a] * rinv;
+    ke_i += qi[1 + a] * vi[a];
   }
-  qb[0] = rb;
-  for (int a = 0; a < 3; ++a) qb[1 + a] = rb * ub[a];
-  qb[4] = pb / (g - 1.0) + 0.5 * rb * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+  const double p_i = gm1 * (qi[4] - 0.5 * ke_i);
+  const double c_i = sqrt(g * p_i * rinv);
+  const double un_i = vi[0] * nh[0] + vi[1] * nh[1] + vi[2] * nh[2];
+  const double un_inf = mach_inf * nh[0];  // free-stream normal velocity, sound speed 1
+  if (un_i >= c_i) {  // supersonic outflow
+    for (int v = 0; v < 5; ++v) qb[v] = qi[v];
+    return;
+  }
+  if (un_i <= -c_i) {  // supersonic inflow
+    qb[0] = 1.0;
+    qb[1] = mach_inf;
+    qb[2] = 0.0;
+    qb[3] = 0.0;
+    qb[4] = 1.0 / (g * gm1) + 0.5 * mach_inf * mach_inf;
+    return;
+  }
+  const double out_inv = un_i + 2.0 * c_i / gm1;  // leaves through the face
+  const double in_inv = un_inf - 2.0 / gm1;       // enters from the free stream
+  const double un_b = 0.5 * (out_inv + in_inv);
+  const double c_b = 0.25 * gm1 * (out_inv - in_inv);
+  // the upwind state w: density, sound speed, velocity and its normal part
+  const bool outflow = un_b > 0.0;
+  const double rho_w = outflow ? qi[0] : 1.0;
+  const double c_w = outflow ? c_i : 1.0;
+  const double vw[3] = {outflow ? vi[0] : mach_inf, outflow ? vi[1] : 0.0, outflow ? vi[2] : 0.0};
+  const double un_w = outflow ? un_i : un_inf;
+  const double rho_b = rho_w * pow(c_b / c_w, 2.0 / gm1);
+  double ke_b = 0.0;
+  qb[0] = rho_b;
+  for (int a = 0; a < 3; ++a) {
+    const double vb = vw[a] + (un_b - un_w) * nh[a];  // tangential part of w, normal part from the invariants
+    qb[1 + a] = rho_b * vb;
+    ke_b += vb * vb;
+  }
+  qb[4] = rho_b * c_b * c_b / (g * gm1) + 0.5 * rho_b * ke_b;  // p = rho a^2 / gamma
 }
 
 // Centreline: the average over all azimuths of ring j = 2 of each conserved
