@@ -53,7 +53,8 @@ hipError_t launch_finalize_step(Clock* clk, const double* norm_part, const doubl
                                 int* flag, hipStream_t st);
 hipError_t launch_reset_clock(Clock* clk, int* flag, hipStream_t st);
 hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_t st);
-hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, hipStream_t st);
+hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, double* part_red,
+                                  hipStream_t st);
 hipError_t launch_halo_jobs(const HaloJob* jobs, int njobs, bool is_float, int d, long long max_count,
                             hipStream_t st);
 hipError_t launch_export_clock(const Clock* clk, const int* flag, double* out, hipStream_t st);
@@ -1776,7 +1777,8 @@ struct jz_domain {
   BatchCtl* d_ctl;
   HaloJob* d_jobs;
   int job_off[3][2], njobs[3][2];
-  long long job_max[3][2];
+  long long job_max[3][2];  // threads of the largest job of each pass
+  double* d_red;            // [parts][11]: per-part norm sums, maxima, spectral radius
 };
 
 namespace {
@@ -1881,7 +1883,8 @@ int dom_build_launch_tables(jz_domain* D) {
             J.dl0 = side == 0 ? 0 : J.nd[d] - 2;
             J.sl0 = side == 0 ? J.nsrc[d] - 4 : 2;
             jobs.push_back(J);
-            const long long cnt = 2LL * J.nd[face_e(d)] * J.nd[face_f(d)] * 5;
+            // ten threads per ghost row along xi, one per value otherwise
+            const long long cnt = d == 0 ? 10LL * J.nd[1] * J.nd[2] : 2LL * J.nd[face_e(d)] * J.nd[face_f(d)] * 5;
             if (cnt > D->job_max[kind][pass]) D->job_max[kind][pass] = cnt;
             D->njobs[kind][pass] += 1;
           }
@@ -1993,6 +1996,7 @@ int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, in
   D->d_off = nullptr;
   D->d_ctl = nullptr;
   D->d_jobs = nullptr;
+  D->d_red = nullptr;
   // balanced parts: sizes differ by at most one node, larger ones first
   for (int d = 0; d < 3; ++d) {
     const int np = D->parts[d];
@@ -2027,6 +2031,7 @@ int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, in
       D->sub.push_back(s);
     }
   hipError_t e = hipMalloc((void**)&D->d_sub, D->sub.size() * sizeof(DomainSub));
+  if (e == hipSuccess) e = hipMalloc((void**)&D->d_red, D->sub.size() * 11 * sizeof(double));
   if (e != hipSuccess) {
     jz_domain_destroy(D);
     return fail(JZ_ENOMEM, "jz_domain_create: %s", hipGetErrorString(e));
@@ -2092,7 +2097,7 @@ int jz_domain_advance(jz_domain* D, int nsteps) {
       if (rc) return rc;
     }
     HIP_TRY(launch_domain_finalize(D->d_sub, (int)D->sub.size(), dom_ctl(D), D->batched ? D->d_ctl : nullptr,
-                                   D->stream));
+                                   D->d_red, D->stream));
   }
   return JZ_OK;
 }
@@ -2134,6 +2139,7 @@ int jz_domain_destroy(jz_domain* D) {
   if (D->d_off) (void)hipFree(D->d_off);
   if (D->d_ctl) (void)hipFree(D->d_ctl);
   if (D->d_jobs) (void)hipFree(D->d_jobs);
+  if (D->d_red) (void)hipFree(D->d_red);
   delete D;
   return JZ_OK;
 }

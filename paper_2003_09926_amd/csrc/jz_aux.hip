@@ -554,14 +554,26 @@ template <typename T>
 __global__ __launch_bounds__(256) void halo_jobs_kernel(const HaloJob* __restrict__ jobs, int d) {
   const HaloJob& J = jobs[blockIdx.y];
   const int e = face_e(d), f = face_f(d);
-  const long long count = 2LL * J.nd[e] * J.nd[f] * 5;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const int v = (int)(t % 5);
-  const long long node = t / 5;
   const long long face = (long long)J.nd[e] * J.nd[f];
-  const int layer = (int)(node / face);
-  const long long r = node % face;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d == 0) {
+    // along xi the two ghost layers of a row are neighbouring nodes, ten
+    // contiguous values: ten consecutive threads copy them
+    if (t >= face * 10) return;
+    const long long row = t / 10;
+    const int q = (int)(t % 10);
+    const int j = (int)(row % J.nd[1]), k = (int)(row / J.nd[1]);
+    const long long id = J.dl0 + (long long)J.nd[0] * (j + (long long)J.nd[1] * k);
+    const long long is = J.sl0 + (long long)J.nsrc[0] * (j + (long long)J.nsrc[1] * k);
+    static_cast<T*>(J.dst)[5 * id + q] = static_cast<const T*>(J.src)[5 * is + q];
+    return;
+  }
+  // along eta or zeta the face planes are contiguous: one thread per value,
+  // the five values of a node, then the face nodes, then the layer
+  if (t >= 2 * face * 5) return;
+  const int v = (int)(t % 5);
+  const int layer = (int)((t / 5) / face);
+  const long long r = (t / 5) % face;
   int c[3];
   c[e] = (int)(r % J.nd[e]);
   c[f] = (int)(r / J.nd[e]);
@@ -601,24 +613,45 @@ __global__ __launch_bounds__(FIN_T) void domain_dt_kernel(const DomainSub* __res
   }
 }
 
-// End of a domain step: the first-stage norms over all sub-blocks (sub-block
-// by sub-block, each in its fixed tile order), the clock advanced by the dt
+// First level of a domain step's reductions, one workgroup per sub-block:
+// its first-stage norm sums and maxima and its largest spectral radius, each
+// in the sub-block's fixed tile order, to part_red[p][0..10].
+__global__ __launch_bounds__(FIN_T) void domain_part_reduce_kernel(const DomainSub* __restrict__ sub,
+                                                                   double* __restrict__ part_red) {
+  __shared__ double red[FIN_T];
+  const DomainSub& S = sub[blockIdx.x];
+  double* out = part_red + 11 * blockIdx.x;
+  for (int v = 0; v < 5; ++v) {
+    const double sv = block_sum(S.norm_part + v, 10, S.nb_tiles, red);
+    const double mv = block_max(S.norm_part + 5 + v, 10, S.nb_tiles, red);
+    if (threadIdx.x == 0) {
+      out[v] = sv;
+      out[5 + v] = mv;
+    }
+  }
+  const double lm = block_max(S.lam_part, 1, S.nb_tiles, red);
+  if (threadIdx.x == 0) out[10] = lm;
+}
+
+// End of a domain step: the first-stage norms over all sub-blocks (their
+// first-level results added in sub-block order), the clock advanced by the dt
 // just used, and the next dt from the last stage's lambda maxima of all
 // sub-blocks -- the same values in every sub-block's clock.
 __global__ __launch_bounds__(FIN_T) void domain_finalize_kernel(const DomainSub* __restrict__ sub, int P,
-                                                                StepCtl ctl, BatchCtl* __restrict__ work) {
-  __shared__ double red[FIN_T];
+                                                                StepCtl ctl, BatchCtl* __restrict__ work,
+                                                                const double* __restrict__ part_red) {
   // the tile counters of the batched stage launches, for the next step
   if (work && threadIdx.x < 5 * kBatchSlots) (&work->next[0][0])[threadIdx.x] = 0;
   for (int p = 0; p < P; ++p)
     if (*sub[p].flag) return;  // a failed step froze the state
+  // second level: the parts' results in part order
   double sums[5] = {0, 0, 0, 0, 0}, maxs[5] = {0, 0, 0, 0, 0}, lmax = 0.0;
   for (int p = 0; p < P; ++p) {
     for (int v = 0; v < 5; ++v) {
-      sums[v] += block_sum(sub[p].norm_part + v, 10, sub[p].nb_tiles, red);
-      maxs[v] = max_nan(maxs[v], block_max(sub[p].norm_part + 5 + v, 10, sub[p].nb_tiles, red));
+      sums[v] += part_red[11 * p + v];
+      maxs[v] = max_nan(maxs[v], part_red[11 * p + 5 + v]);
     }
-    lmax = max_nan(lmax, block_max(sub[p].lam_part, 1, sub[p].nb_tiles, red));
+    lmax = max_nan(lmax, part_red[11 * p + 10]);
   }
   if (threadIdx.x == 0) {
     bool ok = isfinite(lmax);
@@ -645,8 +678,11 @@ hipError_t launch_domain_dt(const DomainSub* sub, int P, StepCtl ctl, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, hipStream_t st) {
-  hipLaunchKernelGGL(domain_finalize_kernel, dim3(1), dim3(FIN_T), 0, st, sub, P, ctl, work);
+hipError_t launch_domain_finalize(const DomainSub* sub, int P, StepCtl ctl, BatchCtl* work, double* part_red,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(domain_part_reduce_kernel, dim3(P), dim3(FIN_T), 0, st, sub, part_red);
+  hipLaunchKernelGGL(domain_finalize_kernel, dim3(1), dim3(FIN_T), 0, st, sub, P, ctl, work,
+                     (const double*)part_red);
   return hipGetLastError();
 }
 
