@@ -187,3 +187,57 @@ def test_fullsize_cylinder_centreline_one_step():
         assert np.all(err <= bound), (i0, float(np.max(err - bound)))
         # the axis nodes of the station agree over the azimuth
         assert np.all(gg[:, :, 0] == gg[:, :1, 0])
+
+
+def test_fullsize_batch_mix_sampled_parity():
+    """The benchmark's batch at full size: the 64 uneven jet boxes of the
+    seed-4 mix (each of ni, nj, nk in [32, 160], 60M nodes, own Mach, Re and
+    CFL dt), autotuned as the benchmark does and advanced one step by the
+    persistent batch launch.  Every member's dt equals the oracle's CFL dt of
+    that member, and at three sampled nodes per member (one on a corner of the
+    block, where the tiles and chunks are ragged) the increment matches the
+    oracle stepping the periodic patch around the node."""
+    import torch
+    from paper_2003_09926_amd import binding as B
+    assert torch.cuda.is_available()
+    print("[gpu-case] full-size batch, seed-4 mix of 64 boxes, one step", flush=True)
+    mix = I.batch_mix(seed=4)
+    cases, members = [], []
+    for blk in mix:
+        g = I.uniform_box(*blk["dims"])
+        q = I.jet_state(g, blk["mach"], blk["seed"])
+        s = B.Solver(g.dims, B.params_default(mach_j=blk["mach"], re_d=blk["re_d"], tile_i=28, tile_j=12))
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        cases.append((g, q, blk))
+        members.append(s)
+    with B.Batch(members) as b:
+        choice, _ = b.autotune(trial_steps=2)
+        print(f"[gpu-case] autotuned tile and chunk {choice}", flush=True)
+        b.advance(1)
+        b.synchronize()
+    rng = np.random.default_rng(16)
+    centre = R + (2 * R + 1) * (R + (2 * R + 1) * R)
+    worst = 0.0
+    for s, (g, q, blk) in zip(members, cases):
+        dims = g.dims
+        P = oracle.default_params(mach_j=blk["mach"], re_d=blk["re_d"])
+        dt, _ = oracle.cfl_dt(dims, P, g.metrics, q)
+        t, _, _ = s.clock()
+        assert abs(t - dt) <= 1e-13 * dt, blk
+        qg = s.get_state()
+        s.close()
+        pts = [(dims[0] - 1, dims[1] - 1, dims[2] - 1)]
+        pts += [tuple(int(rng.integers(0, d)) for d in dims) for _ in range(2)]
+        for c in pts:
+            qp = patch(q, dims, c, R)
+            mp = patch(g.metrics, dims, c, R)
+            q1, _, _, _ = oracle.step((2 * R + 1,) * 3, P, mp, qp, dt=dt)
+            n = flat(dims, *c)
+            for v in range(5):
+                inc_o = q1[v, centre] - qp[v, centre]
+                inc_g = qg[v, n] - q[v, n]
+                err = abs(inc_g - inc_o)
+                worst = max(worst, err)
+                assert err <= 1e-9 * abs(inc_o) + 1e-15 * (1 + abs(q[v, n])), (blk["dims"], c, v, inc_g, inc_o)
+    print(f"[gpu-case] worst abs increment error {worst:.3e}", flush=True)
