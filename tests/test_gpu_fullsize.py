@@ -241,3 +241,44 @@ def test_fullsize_batch_mix_sampled_parity():
                 worst = max(worst, err)
                 assert err <= 1e-9 * abs(inc_o) + 1e-15 * (1 + abs(q[v, n])), (blk["dims"], c, v, inc_g, inc_o)
     print(f"[gpu-case] worst abs increment error {worst:.3e}", flush=True)
+
+
+def test_fullsize_fp32_flux_one_step_sampled():
+    """The FP32-flux form at full size in the benchmark's launch shape (32 x 16
+    tiles, one chunk of all 256 planes): dt, computed in FP64 from the double
+    state and the float metrics, within 5e-7 (eight float ulps) of the
+    oracle's, and at the sampled nodes each
+    variable's increment is within 1e-4 of that variable's largest sampled
+    oracle increment -- float rounding of the stage states and fluxes (about
+    6e-8 relative), amplified by the cancellation in the flux differences."""
+    import torch
+    from paper_2003_09926_amd import binding as B
+    assert torch.cuda.is_available()
+    print("[gpu-case] full size 512x256x256 one step, FP32-flux", flush=True)
+    g, q = I.stretched_jet_case(DIMS, seed=2)
+    P = oracle.default_params(re_d=1.0e6)
+    dt, _ = oracle.cfl_dt(g.dims, P, g.metrics, q)
+    with B.Solver(g.dims, B.params_default(re_d=1.0e6, precision=B.JZ_FP32_FLUX)) as s:
+        s.set_grid_metrics(g.metrics)
+        s.set_state(q)
+        print(f"[gpu-case] tiling {s.tiling()}", flush=True)
+        dtg, _ = s.eval_dt()
+        s.advance(1)
+        qg = s.get_state()
+    print(f"[gpu-case] dt relative difference {abs(dtg - dt) / dt:.2e}", flush=True)
+    assert abs(dtg - dt) <= 5e-7 * dt
+    rng = np.random.default_rng(12)
+    centre = R + (2 * R + 1) * (R + (2 * R + 1) * R)
+    inc_o, inc_g = [], []
+    for c in _samples(DIMS, rng):
+        qp = patch(q, DIMS, c, R)
+        mp = patch(g.metrics, DIMS, c, R)
+        q1, _, _, _ = oracle.step((2 * R + 1,) * 3, P, mp, qp, dt=dt)
+        n = flat(DIMS, *c)
+        inc_o.append(q1[:, centre] - qp[:, centre])
+        inc_g.append(qg[:, n] - q[:, n])
+    inc_o, inc_g = np.array(inc_o), np.array(inc_g)
+    scale = np.max(np.abs(inc_o), axis=0)
+    ratio = np.max(np.abs(inc_g - inc_o), axis=0) / scale
+    print(f"[gpu-case] max increment error / largest increment per variable {ratio}", flush=True)
+    assert np.all(ratio <= 1e-4), ratio
