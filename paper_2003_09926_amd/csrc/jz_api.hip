@@ -1899,7 +1899,8 @@ int dom_build_launch_tables(jz_domain* D) {
   // again in its first and last stages, which costs more than the tails of
   // one launch per part (split 2 x 2 at 512 x 256 x 256: 11 % against 10 %
   // over the unsplit block); in FP64 the batched launch took the overhead
-  // from 13 % to 6 %.
+  // from 13 % to 6 % (5 % with the row-wise xi copies and the two-level
+  // step reductions).
   D->bx = D->sub[0]->tl.bx;
   D->by = D->sub[0]->tl.by;
   bool same = true;

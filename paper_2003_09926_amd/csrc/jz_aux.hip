@@ -642,6 +642,7 @@ __global__ __launch_bounds__(FIN_T) void domain_finalize_kernel(const DomainSub*
                                                                 const double* __restrict__ part_red) {
   // the tile counters of the batched stage launches, for the next step
   if (work && threadIdx.x < 5 * kBatchSlots) (&work->next[0][0])[threadIdx.x] = 0;
+  if (threadIdx.x != 0) return;
   for (int p = 0; p < P; ++p)
     if (*sub[p].flag) return;  // a failed step froze the state
   // second level: the parts' results in part order
@@ -653,23 +654,21 @@ __global__ __launch_bounds__(FIN_T) void domain_finalize_kernel(const DomainSub*
     }
     lmax = max_nan(lmax, part_red[11 * p + 10]);
   }
-  if (threadIdx.x == 0) {
-    bool ok = isfinite(lmax);
-    for (int v = 0; v < 5; ++v) ok = ok && isfinite(sums[v]) && isfinite(maxs[v]);
-    const double dt = dt_rule(ctl, lmax);
-    ok = ok && isfinite(dt) && dt > 0.0;
-    for (int p = 0; p < P; ++p) {
-      Clock* c = sub[p].clock;
-      for (int v = 0; v < 5; ++v) {
-        c->rms[v] = sqrt(sums[v] * ctl.inv_n);
-        c->linf[v] = maxs[v];
-      }
-      c->t += c->dt;
-      c->steps += 1;
-      c->lam_max = lmax;
-      c->dt = dt;
-      if (!ok) *sub[p].flag |= 1;
+  bool ok = isfinite(lmax);
+  for (int v = 0; v < 5; ++v) ok = ok && isfinite(sums[v]) && isfinite(maxs[v]);
+  const double dt = dt_rule(ctl, lmax);
+  ok = ok && isfinite(dt) && dt > 0.0;
+  for (int p = 0; p < P; ++p) {
+    Clock* c = sub[p].clock;
+    for (int v = 0; v < 5; ++v) {
+      c->rms[v] = sqrt(sums[v] * ctl.inv_n);
+      c->linf[v] = maxs[v];
     }
+    c->t += c->dt;
+    c->steps += 1;
+    c->lam_max = lmax;
+    c->dt = dt;
+    if (!ok) *sub[p].flag |= 1;
   }
 }
 
