@@ -1251,6 +1251,7 @@ int batch_tables(jz_batch* b) {
   b->stage_next = (si + 1) % jz_batch::kStage;
   HIP_TRY(hipEventSynchronize(b->ev_stage[si]));  // the buffer's previous copy is done
   char* h = b->h_stage[si];
+  if (!h) return fail(JZ_ENOMEM, "batch tables: no staging buffer (an earlier allocation failed)");
   BlockDesc* d = reinterpret_cast<BlockDesc*>(h + stage_desc_ofs(b->cap));
   int* off = reinterpret_cast<int*>(h + stage_off_ofs());
   BatchCtl& c = *reinterpret_cast<BatchCtl*>(h);
@@ -1691,6 +1692,7 @@ int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int*
         }
         if (rc == JZ_OK) rc = restore();
       }
+    if (rc) (void)restore();  // a failed trial leaves the states as they were
     jz_batch_set_timing(b, timing_was ? 1 : 0);
     for (double* p : qsave)
       if (p) (void)hipFree(p);
@@ -1704,9 +1706,19 @@ int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int*
       }
     }
   }
-  for (jz_solver* s : b->m) {
-    int rc = jz_set_tiling(s, best_ti, best_tj, best_kc);
-    if (rc) return rc;
+  // apply the choice to every member, or to none (a cached choice that a
+  // member does not take leaves the batch as it was)
+  std::vector<std::pair<jz_params, Tiling>> old;
+  for (jz_solver* s : b->m) old.emplace_back(s->p, s->tl);
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    int rc = jz_set_tiling(b->m[i], best_ti, best_tj, best_kc);
+    if (rc) {
+      for (size_t j = 0; j < i; ++j) {
+        b->m[j]->p = old[j].first;
+        b->m[j]->tl = old[j].second;
+      }
+      return rc;
+    }
   }
   b->bx = best_ti + 4;
   b->by = best_tj + 4;

@@ -129,6 +129,41 @@ def test_autotune_keeps_results(B, tmp_path):
     assert open(cache).read().count("\n") == 1
 
 
+def _tune_key(prec, ns, dims):
+    """The batch signature the autotuner files its choices under."""
+    h = 1469598103934665603
+    for v in sorted((ni << 40) | (nj << 20) | nk for ni, nj, nk in dims):
+        h = ((h ^ v) * 1099511628211) % (1 << 64)
+    return f"p{prec}-s{ns}-n{len(dims)}-{h:016x}"
+
+
+def test_autotune_rejects_unusable_cached_choice(B, tmp_path):
+    """A cache line whose tile shape has no stage kernel is refused: the call
+    fails, every member keeps its launch shape, and the batch still steps to
+    the same states as the members alone."""
+    print("[gpu-case] batch autotune, unusable cached choice", flush=True)
+    cases = _cases()[:3]
+    ref = []
+    for s in _members(B, cases, 0, (16, 12)):
+        s.advance(2)
+        ref.append(s.get_state())
+        s.close()
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{_tune_key(0, 5, [g.dims for g, _, _ in cases])} 15 7 32 1.0\n")
+    ms = _members(B, cases, 0, (16, 12))
+    before = [s.tiling() for s in ms]
+    with B.Batch(ms) as b:
+        with pytest.raises(B.JzError) as ei:
+            b.autotune(trial_steps=1, cache_path=str(cache))
+        assert ei.value.code == B.JZ_EINVAL
+        assert [s.tiling() for s in ms] == before
+        b.advance(2)
+        b.synchronize()
+    for s, q in zip(ms, ref):
+        assert np.array_equal(s.get_state(), q)
+        s.close()
+
+
 def test_failing_member_is_isolated(B):
     """One member with a fixed dt far beyond stability blows up; it is
     flagged and frozen, the others match their solo runs bitwise."""
