@@ -198,75 +198,85 @@ class JetServer:
                 used -= r.footprint
             collect_s += time.perf_counter() - tc
 
-        while pending or resident or finishing:
-            # admission: arrived, a free slot, the footprint fits the budget,
-            # and the resident runs do not fill the device yet; the payload
-            # upload overlaps the steps already queued
-            while pending and pending[0].arrival * time_scale <= now() and len(resident) < self.max_resident:
-                if resident and self.fill_tiles is not None and used_tiles >= self.fill_tiles:
-                    break
-                r = pending[0]
-                fp = footprint(r, self.precision, self.tile, self.kchunk)
-                if fp > self.budget:
-                    pending.popleft()          # can never fit: reject
-                    r.ok, r.finished = False, now()
-                    failed += 1
-                    continue
-                if used + fp > self.budget:
-                    break
-                pending.popleft()
-                tu = time.perf_counter()
-                r.footprint = fp
-                r.stream = torch.cuda.Stream() if self.mode == "streams" else None
-                r.solver = start_run(r, self.precision, self.tile, self.kchunk, stream=r.stream)
-                r.tiles = stage_tiles(r.solver)
-                if self.fill_tiles is None:
-                    _, cus = r.solver.occupancy()
-                    self.fill_tiles = int(self.tiles_per_cu * cus)
-                if self.mode == "batch":
-                    if batch is None:
-                        batch = B.Batch([r.solver])
-                        batch.set_timing(True)
+        try:
+            while pending or resident or finishing:
+                # admission: arrived, a free slot, the footprint fits the budget,
+                # and the resident runs do not fill the device yet; the payload
+                # upload overlaps the steps already queued
+                while pending and pending[0].arrival * time_scale <= now() and len(resident) < self.max_resident:
+                    if resident and self.fill_tiles is not None and used_tiles >= self.fill_tiles:
+                        break
+                    r = pending[0]
+                    fp = footprint(r, self.precision, self.tile, self.kchunk)
+                    if fp > self.budget:
+                        pending.popleft()          # can never fit: reject
+                        r.ok, r.finished = False, now()
+                        failed += 1
+                        continue
+                    if used + fp > self.budget:
+                        break
+                    pending.popleft()
+                    tu = time.perf_counter()
+                    r.footprint = fp
+                    r.stream = torch.cuda.Stream() if self.mode == "streams" else None
+                    r.solver = start_run(r, self.precision, self.tile, self.kchunk, stream=r.stream)
+                    r.tiles = stage_tiles(r.solver)
+                    if self.fill_tiles is None:
+                        _, cus = r.solver.occupancy()
+                        self.fill_tiles = int(self.tiles_per_cu * cus)
+                    if self.mode == "batch":
+                        if batch is None:
+                            batch = B.Batch([r.solver])
+                            batch.set_timing(True)
+                        else:
+                            batch.add(r.solver)
+                    upload_s += time.perf_counter() - tu
+                    r.admitted = now()
+                    r.remaining = r.steps
+                    used += fp
+                    used_tiles += r.tiles
+                    resident.append(r)
+                max_res = max(max_res, len(resident))
+                max_bytes = max(max_bytes, used)
+                earlier, finishing = finishing, []
+                if resident:
+                    # Enqueue the next chunk without waiting for the device: the
+                    # host knows every run's progress, and the streams order the work.
+                    n = min(self.chunk, min(r.remaining for r in resident))
+                    if self.mode == "batch":
+                        batch.advance(n)
                     else:
-                        batch.add(r.solver)
-                upload_s += time.perf_counter() - tu
-                r.admitted = now()
-                r.remaining = r.steps
-                used += fp
-                used_tiles += r.tiles
-                resident.append(r)
-            max_res = max(max_res, len(resident))
-            max_bytes = max(max_bytes, used)
-            earlier, finishing = finishing, []
-            if resident:
-                # Enqueue the next chunk without waiting for the device: the
-                # host knows every run's progress, and the streams order the work.
-                n = min(self.chunk, min(r.remaining for r in resident))
-                if self.mode == "batch":
-                    batch.advance(n)
-                else:
-                    for r in resident:
-                        r.solver.advance(n)
-                chunks += 1
-                point_stages += sum(r.points for r in resident) * 5.0 * n
-                for r in list(resident):
-                    r.remaining -= n
-                    if r.remaining == 0:
-                        if batch is not None:
-                            batch.remove(r.solver)   # no wait: its stream follows this chunk
-                        resident.remove(r)
-                        used_tiles -= r.tiles
-                        finishing.append(r)
-            # read the runs that finished in the previous chunk while the
-            # device works on this one (all of them if nothing is queued)
-            collect(earlier)
-            if not resident:
-                collect(finishing)
-                finishing = []
-                if pending and not resident:
-                    wait = pending[0].arrival * time_scale - now()
-                    if wait > 0:
-                        time.sleep(min(wait, 0.05))
+                        for r in resident:
+                            r.solver.advance(n)
+                    chunks += 1
+                    point_stages += sum(r.points for r in resident) * 5.0 * n
+                    for r in list(resident):
+                        r.remaining -= n
+                        if r.remaining == 0:
+                            if batch is not None:
+                                batch.remove(r.solver)   # no wait: its stream follows this chunk
+                            resident.remove(r)
+                            used_tiles -= r.tiles
+                            finishing.append(r)
+                # read the runs that finished in the previous chunk while the
+                # device works on this one (all of them if nothing is queued)
+                collect(earlier)
+                if not resident:
+                    collect(finishing)
+                    finishing = []
+                    if pending and not resident:
+                        wait = pending[0].arrival * time_scale - now()
+                        if wait > 0:
+                            time.sleep(min(wait, 0.05))
+        except BaseException:
+            # release what is on the device before the error propagates
+            if batch is not None:
+                batch.close()
+            for r in resident + finishing:
+                if r.solver is not None:
+                    r.solver.close()
+                    r.solver = None
+            raise
         gpu_step_s = None
         if batch is not None:
             batch.synchronize()
