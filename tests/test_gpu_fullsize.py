@@ -285,31 +285,34 @@ def test_fullsize_fp32_flux_one_step_sampled():
 
 
 @pytest.mark.timeout(900)
-def test_largest_block_64bit_offsets():
+@pytest.mark.parametrize("prec", [0, 1])
+def test_largest_block_64bit_offsets(prec):
     """A block past the 32-bit element offsets: 1024 x 512 x 832 nodes (436M,
-    87 GB of FP64 workspace), so that 5 N values per array exceed 2^31.  One
-    step of the jet box; dt against the oracle's CFL dt, and increments at
-    sampled nodes -- the last node and nodes whose value offsets lie beyond
-    2^31 among them -- against the oracle stepping the patch around them."""
+    87 GB of FP64 workspace, 72 GB in the FP32-flux form), so that 5 N values
+    per array exceed 2^31.  One step of the jet box; dt against the oracle's
+    CFL dt, and increments at sampled nodes -- the last node and nodes whose
+    value offsets lie beyond 2^31 among them -- against the oracle stepping
+    the patch around them: FP64 at the full-size bars, FP32-flux at its own
+    (dt within 5e-7, increments within 1e-4 of the largest sampled one)."""
     import torch
     from paper_2003_09926_amd import binding as B
     assert torch.cuda.is_available()
     dims = (1024, 512, 832)
     n_all = dims[0] * dims[1] * dims[2]
     assert 5 * n_all > 2 ** 31
-    print(f"[gpu-case] largest block {dims}, {n_all} nodes, one step", flush=True)
+    print(f"[gpu-case] largest block {dims}, {n_all} nodes, one step, precision={prec}", flush=True)
     g, q = I.jet_box_case(dims, seed=6)
     m = g.metrics
     del g
     P = oracle.default_params()
     dt, _ = oracle.cfl_dt(dims, P, m, q)
-    with B.Solver(dims, B.params_default()) as s:
+    with B.Solver(dims, B.params_default(precision=prec)) as s:
         s.set_grid_metrics(m)
         s.set_state(q)
         s.advance(1)
         qg = s.get_state()
         t, _, _ = s.clock()
-    assert abs(t - dt) <= 1e-13 * dt
+    assert abs(t - dt) <= (1e-13 if prec == 0 else 5e-7) * dt
     rng = np.random.default_rng(18)
     first_far = -(-(2 ** 31) // 5)        # first node whose value offsets pass 2^31
     pts = [(dims[0] - 1, dims[1] - 1, dims[2] - 1), (0, 0, 0)]
@@ -317,13 +320,19 @@ def test_largest_block_64bit_offsets():
         n = int(rng.integers(first_far, n_all))
         pts.append((n % dims[0], (n // dims[0]) % dims[1], n // (dims[0] * dims[1])))
     centre = R + (2 * R + 1) * (R + (2 * R + 1) * R)
+    inc_o, inc_g, q_n = [], [], []
     for c in pts:
         qp = patch(q, dims, c, R)
         mp = patch(m, dims, c, R)
         q1, _, _, _ = oracle.step((2 * R + 1,) * 3, P, mp, qp, dt=dt)
         n = flat(dims, *c)
-        for v in range(5):
-            inc_o = q1[v, centre] - qp[v, centre]
-            inc_g = qg[v, n] - q[v, n]
-            assert abs(inc_g - inc_o) <= 1e-9 * abs(inc_o) + 1e-15 * (1 + abs(q[v, n])), (c, v, inc_g, inc_o)
+        inc_o.append(q1[:, centre] - qp[:, centre])
+        inc_g.append(qg[:, n] - q[:, n])
+        q_n.append(q[:, n])
+    inc_o, inc_g, q_n = np.array(inc_o), np.array(inc_g), np.array(q_n)
+    err = np.abs(inc_g - inc_o)
+    if prec == 0:
+        assert np.all(err <= 1e-9 * np.abs(inc_o) + 1e-15 * (1 + np.abs(q_n))), err
+    else:
+        assert np.all(np.max(err, axis=0) <= 1e-4 * np.max(np.abs(inc_o), axis=0)), err
     print("[gpu-case] largest block ok", flush=True)
