@@ -31,11 +31,16 @@
 // closed forms and invariants in tests/test_oracle_pins.py (free-stream
 // preservation, discrete conservation, isentropic vortex, second-order
 // convergence, shear-wave and entropy-wave decay factors, Smagorinsky closed
-// form, mirror symmetry) and the boundary treatment in
-// tests/test_oracle_bc_pins.py (Riemann-invariant identities, free-stream
-// preservation and conservation on bounded blocks, transparency to an
-// outgoing acoustic pulse).  The numerical values of the open constants are
-// "parity unpinned" against the paper, which prints none.
+// form, mirror symmetry), the viscous closure and the shock branch of the
+// dissipation in tests/test_oracle_closure_pins.py (heat conduction, the
+// -2/3 div u stress, the viscous work in the energy flux, each against its
+// Fourier-mode closed form; a periodic Sod pair against the exact Riemann
+// solution with the fourth-difference coefficient clamped at the shocks)
+// and the boundary treatment in tests/test_oracle_bc_pins.py
+// (Riemann-invariant identities, free-stream preservation and conservation
+// on bounded blocks, transparency to an outgoing acoustic pulse).  The
+// numerical values of the open constants are "parity unpinned" against the
+// paper, which prints none.
 #include <cmath>
 #include <cstddef>
 #ifdef _OPENMP
