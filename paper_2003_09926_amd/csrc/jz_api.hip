@@ -1163,8 +1163,12 @@ struct jz_batch {
   long long steps_acc;
   // Pinned staging buffers of the table uploads, each with the event of its
   // last copy: a change of the member set is queued on the batch's stream
-  // behind the steps in flight instead of waiting for them.
-  static constexpr int kStage = 4;
+  // behind the steps in flight instead of waiting for them.  A buffer is
+  // reused only after kStage later changes, so the host waits only when that
+  // many changes are queued behind unfinished steps (a server changes the set
+  // a few times per chunk of steps; with four buffers the removals of runs
+  // finishing together waited for the chunk just queued).
+  static constexpr int kStage = 32;
   char* h_stage[kStage];
   hipEvent_t ev_stage[kStage];
   size_t stage_bytes;

@@ -218,7 +218,11 @@ class JetServer:
                     pending.popleft()
                     tu = time.perf_counter()
                     r.footprint = fp
-                    r.stream = torch.cuda.Stream() if self.mode == "streams" else None
+                    # every run uploads, and is read back, on a stream of its
+                    # own: after a removal the run's stream waits for the
+                    # batch's queued steps, and a stream shared with the next
+                    # admissions would hold their uploads behind those steps
+                    r.stream = torch.cuda.Stream()
                     r.solver = start_run(r, self.precision, self.tile, self.kchunk, stream=r.stream)
                     r.tiles = stage_tiles(r.solver)
                     if self.fill_tiles is None:
