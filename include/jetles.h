@@ -262,9 +262,11 @@ int jz_batch_advance(jz_batch* b, int nsteps);
  * batch's next step).  remove: takes the member out; work issued afterwards
  * on the member's own stream follows the batch steps queued so far (the
  * last ones that include it); the caller keeps the solver.  Neither call
- * waits for the device: the table change is queued behind the steps in
- * flight.  A batch may be empty (its steps then do nothing).  members: the
- * current member count. */
+ * waits for the device: the table change is staged in pinned host memory
+ * and queued behind the steps in flight (the call waits only when the
+ * tables must grow, or when 32 earlier changes are still queued behind
+ * unfinished steps).  A batch may be empty (its steps then do nothing).
+ * members: the current member count. */
 int jz_batch_add(jz_batch* b, jz_solver* s);
 int jz_batch_remove(jz_batch* b, jz_solver* s);
 int jz_batch_members(jz_batch* b);
