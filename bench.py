@@ -144,6 +144,49 @@ def _time_solver(s, n_adv: int, steps: int, warmup: int):
             stage_bytes / max(launches, 1))
 
 
+def _rate_gbs(fn, nbytes_moved: int, reps: int = 10) -> float:
+    """GB/s of `nbytes_moved` per call of fn, timed with events over reps
+    calls after three untimed ones."""
+    import torch
+    for _ in range(3):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return nbytes_moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def _stream_rate_gbs(nbytes: int = 2 << 30) -> float:
+    """HBM rate a plain elementwise stream reaches on this GPU: b = 1.0 * a
+    over 2 GiB of float32 (bytes read plus bytes written per second, GB/s),
+    the achievable counterpart of the published peak."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    r = _rate_gbs(lambda: torch.mul(a, 1.0, out=b), 2 * nbytes)
+    del a, b
+    return r
+
+
+def hbm_rates(nbytes: int = 2 << 30) -> dict:
+    """Plain streaming rates of the GPU's HBM (GB/s, bytes read plus bytes
+    written): the runtime's device-to-device copy, an elementwise stream,
+    a read-only sum and a write-only fill, over nbytes."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    out = {"bytes": nbytes,
+           "device_copy": _rate_gbs(lambda: b.copy_(a), 2 * nbytes),
+           "elementwise_stream": _rate_gbs(lambda: torch.mul(a, 1.0, out=b), 2 * nbytes),
+           "read_sum": _rate_gbs(lambda: a.view(torch.float64).sum(), nbytes),
+           "write_fill": _rate_gbs(lambda: b.fill_(1.0), nbytes)}
+    del a, b
+    return out
+
+
 def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bool, stats_interval: int = 0,
               with_secondary: bool = False):
     """fp64 / fp32: the periodic stretched jet block.  domain-fp64 /
@@ -212,6 +255,11 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
                       "potential_core_length": ST.potential_core_length(g.axes[0], axis_u, 1.4),
                       "max_rms_u": float(st["rms_u"].max())}
     s.close()
+    stream_gbs = _stream_rate_gbs()
+    if secondary is not None:
+        r32 = secondary["roofline"]
+        r32["achievable_gbs"] = stream_gbs
+        r32["frac_of_achievable"] = r32["achieved"] / stream_gbs
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernel = "stage_fp64" if prec_name == "fp64" else "stage_fp32flux"
     traffic = None if (domain or cylinder) else _traffic(kernel)
@@ -229,7 +277,8 @@ def run_block(form: str, steps: int, warmup: int, with_cpu: bool, with_error: bo
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "avg_launch_ms": avg_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "achievable_gbs": stream_gbs, "frac_of_achievable": achieved / stream_gbs},
     }
     if stats_info is not None:
         out["stats"] = stats_info
@@ -422,7 +471,12 @@ def main(argv=None):
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run 5 plain device copies of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
+    ap.add_argument("--hbm-rates", action="store_true",
+                    help="instead of the workload, print the HBM rates of plain streaming kernels")
     a = ap.parse_args(argv)
+    if a.hbm_rates:
+        print(json.dumps({"hbm_rates_gbs": [hbm_rates(g << 30) for g in (1, 2, 4, 8)]}), flush=True)
+        return
     if a.copy_calibrate:
         import torch
         n = a.copy_calibrate * (1 << 20) // 8
