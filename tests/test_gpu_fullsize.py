@@ -189,24 +189,29 @@ def test_fullsize_cylinder_centreline_one_step():
         assert np.all(gg[:, :, 0] == gg[:, :1, 0])
 
 
-def test_fullsize_batch_mix_sampled_parity():
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fullsize_batch_mix_sampled_parity(prec):
     """The benchmark's batch at full size: the 64 uneven jet boxes of the
     seed-4 mix (each of ni, nj, nk in [32, 160], 60M nodes, own Mach, Re and
     CFL dt), autotuned as the benchmark does and advanced one step by the
     persistent batch launch.  Every member's dt equals the oracle's CFL dt of
     that member, and at three sampled nodes per member (one on a corner of the
     block, where the tiles and chunks are ragged) the increment matches the
-    oracle stepping the periodic patch around the node."""
+    oracle stepping the periodic patch around the node: FP64 at the full-size
+    bars; FP32-flux with dt within 5e-7 and each variable's increment error
+    within 1e-4 of the member's largest sampled increment."""
     import torch
     from paper_2003_09926_amd import binding as B
     assert torch.cuda.is_available()
-    print("[gpu-case] full-size batch, seed-4 mix of 64 boxes, one step", flush=True)
+    print(f"[gpu-case] full-size batch, seed-4 mix of 64 boxes, one step, precision={prec}", flush=True)
+    tile = (28, 12) if prec == 0 else (28, 20)
     mix = I.batch_mix(seed=4)
     cases, members = [], []
     for blk in mix:
         g = I.uniform_box(*blk["dims"])
         q = I.jet_state(g, blk["mach"], blk["seed"])
-        s = B.Solver(g.dims, B.params_default(mach_j=blk["mach"], re_d=blk["re_d"], tile_i=28, tile_j=12))
+        s = B.Solver(g.dims, B.params_default(mach_j=blk["mach"], re_d=blk["re_d"], precision=prec,
+                                              tile_i=tile[0], tile_j=tile[1]))
         s.set_grid_metrics(g.metrics)
         s.set_state(q)
         cases.append((g, q, blk))
@@ -224,23 +229,31 @@ def test_fullsize_batch_mix_sampled_parity():
         P = oracle.default_params(mach_j=blk["mach"], re_d=blk["re_d"])
         dt, _ = oracle.cfl_dt(dims, P, g.metrics, q)
         t, _, _ = s.clock()
-        assert abs(t - dt) <= 1e-13 * dt, blk
+        assert abs(t - dt) <= (1e-13 if prec == 0 else 5e-7) * dt, blk
         qg = s.get_state()
         s.close()
         pts = [(dims[0] - 1, dims[1] - 1, dims[2] - 1)]
         pts += [tuple(int(rng.integers(0, d)) for d in dims) for _ in range(2)]
+        inc_o, inc_g, q_n = [], [], []
         for c in pts:
             qp = patch(q, dims, c, R)
             mp = patch(g.metrics, dims, c, R)
             q1, _, _, _ = oracle.step((2 * R + 1,) * 3, P, mp, qp, dt=dt)
             n = flat(dims, *c)
-            for v in range(5):
-                inc_o = q1[v, centre] - qp[v, centre]
-                inc_g = qg[v, n] - q[v, n]
-                err = abs(inc_g - inc_o)
-                worst = max(worst, err)
-                assert err <= 1e-9 * abs(inc_o) + 1e-15 * (1 + abs(q[v, n])), (blk["dims"], c, v, inc_g, inc_o)
-    print(f"[gpu-case] worst abs increment error {worst:.3e}", flush=True)
+            inc_o.append(q1[:, centre] - qp[:, centre])
+            inc_g.append(qg[:, n] - q[:, n])
+            q_n.append(q[:, n])
+        inc_o, inc_g, q_n = np.array(inc_o), np.array(inc_g), np.array(q_n)
+        err = np.abs(inc_g - inc_o)
+        if prec == 0:
+            worst = max(worst, float(err.max()))
+            assert np.all(err <= 1e-9 * np.abs(inc_o) + 1e-15 * (1 + np.abs(q_n))), (blk["dims"], err)
+        else:
+            ratio = np.max(err, axis=0) / np.max(np.abs(inc_o), axis=0)
+            worst = max(worst, float(ratio.max()))
+            assert np.all(ratio <= 1e-4), (blk["dims"], ratio)
+    print(f"[gpu-case] worst increment error ({'abs' if prec == 0 else 'relative to the largest'}) "
+          f"{worst:.3e}", flush=True)
 
 
 def test_fullsize_fp32_flux_one_step_sampled():
