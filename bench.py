@@ -488,7 +488,7 @@ def main(argv=None):
         print(json.dumps({"copy_calibrate_bytes_each_way": n * 8, "copies": 5}), flush=True)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs one GPU per process and measures one GPU; "
+        print(json.dumps({"error": "the benchmark runs one GPU per process and measures one GPU; "
                                    "--gpus above 1 is not supported"}), flush=True)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
