@@ -2051,7 +2051,7 @@ int jz_domain_create(int ni, int nj, int nk, const jz_params* p, int parts_i, in
   // so their chunks are chosen for the domain as a whole: 64 planes when all
   // the parts' tiles fill the device with them.  A part on its own would take
   // shorter chunks to fill the device and march more warm-up planes (4 x 4
-  // parts of 512 x 256 x 256: 22 instead of 64 planes, 13 % longer stages).
+  // parts of 512 x 256 x 256: 13 instead of 64 planes, 13 % longer stages).
   if (p->precision == JZ_FP64 && p->kchunk <= 0) {
     bool compact = true;
     long long tiles = 0;
