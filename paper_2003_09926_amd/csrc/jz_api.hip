@@ -1644,7 +1644,7 @@ int jz_batch_autotune(jz_batch* b, int trial_steps, const char* cache_path, int*
     if (b->prec == JZ_FP64)
       cand = {{16, 12}, {32, 8}, {16, 16}, {28, 12}, {12, 12}};
     else
-      cand = {{32, 16}, {28, 20}, {12, 12}};
+      cand = {{32, 16}, {28, 20}, {28, 12}, {12, 12}};
     const int kcs[3] = {16, 32, 64};
     // save states and clocks
     std::vector<double*> qsave(b->m.size(), nullptr);
